@@ -1,0 +1,351 @@
+"""FP64 CPU oracle of the per-frame hot path: lite flow network + consistency step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this module.  It shares no code with
+the HIP path (no kernels, headers, helpers or constants); the two meet only in
+the seeded inputs they are both given.
+
+Everything is plain numpy float64, written for a reader to check against the
+paper by eye; convolutions are im2col in row bands followed by one BLAS matmul,
+the only library primitive used.
+
+What it follows (paper: "Interactive Control over Temporal Consistency while
+Stylizing Video Streams"):
+
+* Sec. 3.1, problem statement: given input frames I and per-frame stylized
+  frames P, produce O with O_1 = P_1 and O_t computed from O_{t-1}.
+* Sec. 3.1, Eq. 4: the global term G_t = Gamma(O_{t-1}), Gamma a backward warp
+  by optical flow.
+* Sec. 3.1, Eq. 5: the blend A_t = w_p G_t + (1 - w_p) L_t, whose upper clamp
+  k_1 of w_p is the interactive share of global consistency ("Consistency
+  Control Modes").  Here the strength alpha takes the role of k_1, w_p is
+  alpha times a binary visibility mask and L_t = P_t; the output is A_t (the
+  limit of Eq. 1 where the smoothness term dominates).  These readings are
+  listed in the design notes.
+* Sec. 5, Eq. 9: the non-occlusion mask is the forward-backward consistency
+  check; its threshold is 0.01 (|f_b|^2 + |f~_f|^2) + 0.5.
+* Sec. 3.2 and supplementary S1: the flow network is PWC-Net-shaped (feature
+  pyramid, warping, correlation, CNN flow estimator per level, coarse to
+  fine) with "light" estimators that keep a dense connection only into the
+  last layer.
+* Supplementary Eq. S1: the end-point error.
+
+Parity status: every op (pad, conv, LeakyReLU, up2, warp, cost volume, mask,
+blend) is pinned by tests/test_oracle.py against closed forms, brute force,
+library routines and exact invariants; the level recursion and the decoder's
+channel order are pinned with constructed weights.  The composition of the
+random-weight network as a whole has no published value to pin against.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# weights
+
+
+def unpack_weights(blob, desc):
+    """Split the flat float32 weight blob into {name: (W, b)} in float64.
+
+    Blob layout, layer after layer: W[cout][cin][3][3] then b[cout].  Order:
+    pyramid convs of level 1..L (stride 2 then stride 1), then the decoder of
+    level 1..L (c1, c2, c3, head).
+    """
+    L, ch, dec, r = desc["levels"], desc["ch"], desc["dec"], desc["radius"]
+    ncv = (2 * r + 1) * (2 * r + 1)
+    names = []
+    for l in range(1, L + 1):
+        names.append((f"pyr{l}a", ch[l - 1], 3 if l == 1 else ch[l - 2]))
+        names.append((f"pyr{l}b", ch[l - 1], ch[l - 1]))
+    for l in range(1, L + 1):
+        names.append((f"dec{l}c1", dec[0], ncv + ch[l - 1] + 2))
+        names.append((f"dec{l}c2", dec[1], dec[0]))
+        names.append((f"dec{l}c3", dec[2], dec[1]))
+        names.append((f"dec{l}head", 2, dec[1] + dec[2]))
+    blob = np.asarray(blob, dtype=np.float64).ravel()
+    out, pos = {}, 0
+    for name, co, ci in names:
+        n = co * ci * 9
+        w = blob[pos:pos + n].reshape(co, ci, 3, 3)
+        pos += n
+        b = blob[pos:pos + co]
+        pos += co
+        out[name] = (w, b)
+    if pos != blob.size:
+        raise ValueError(f"weight blob has {blob.size} floats, layout needs {pos}")
+    return out
+
+
+# --------------------------------------------------------------------------
+# elementary ops
+
+
+def lrelu(z, slope=0.1):
+    """LeakyReLU: z where z >= 0, slope * z elsewhere."""
+    return np.where(z >= 0, z, slope * z)
+
+
+def pad_frame(img, levels):
+    """Edge-replicate the bottom and right borders up to a multiple of 2^L.
+
+    img: (C, H, W).  The network halves the resolution L times, so every
+    level must have integer size.
+    """
+    m = 2 ** levels
+    C, H, W = img.shape
+    Hp, Wp = -(-H // m) * m, -(-W // m) * m
+    return np.pad(img, ((0, 0), (0, Hp - H), (0, Wp - W)), mode="edge")
+
+
+def conv3x3(x, w, b, stride=1, band_bytes=96 << 20):
+    """3x3 cross-correlation with zero padding 1 and the given stride.
+
+    y[o, i, j] = b[o] + sum_{c,p,q} w[o, c, p, q] * x[c, s*i + p - 1, s*j + q - 1]
+
+    x: (Cin, H, W); w: (Cout, Cin, 3, 3); b: (Cout,).  Output rows are
+    produced in bands so the im2col matrix stays within ``band_bytes``.
+    """
+    x = np.asarray(x, np.float64)
+    cin, H, W = x.shape
+    cout = w.shape[0]
+    s = stride
+    Ho, Wo = (H - 1) // s + 1, (W - 1) // s + 1
+    xp = np.pad(x, ((0, 0), (1, 1), (1, 1)))
+    wm = np.asarray(w, np.float64).reshape(cout, cin * 9)
+    out = np.empty((cout, Ho, Wo))
+    band = max(1, int(band_bytes // (cin * 9 * Wo * 8)))
+    for r0 in range(0, Ho, band):
+        r1 = min(Ho, r0 + band)
+        nr = r1 - r0
+        cols = np.empty((cin, 3, 3, nr, Wo))
+        for p in range(3):
+            for q in range(3):
+                cols[:, p, q] = xp[:, s * r0 + p: s * (r1 - 1) + p + 1: s,
+                                   q: q + s * (Wo - 1) + 1: s]
+        out[:, r0:r1] = (wm @ cols.reshape(cin * 9, nr * Wo)).reshape(cout, nr, Wo)
+    out += np.asarray(b, np.float64)[:, None, None]
+    return out
+
+
+def up2(f):
+    """Bilinear 2x upsampling, half-pixel centres (align_corners=False).
+
+    Output index i samples the input at (i + 1/2)/2 - 1/2, clamped to
+    [0, n-1]; separable over rows and columns.  f: (C, h, w) -> (C, 2h, 2w).
+    """
+    def axis_taps(n):
+        src = np.clip((np.arange(2 * n) + 0.5) / 2.0 - 0.5, 0.0, n - 1)
+        i0 = np.floor(src).astype(np.int64)
+        i1 = np.minimum(i0 + 1, n - 1)
+        return i0, i1, src - i0
+
+    C, h, w = f.shape
+    r0, r1, ry = axis_taps(h)
+    c0, c1, rx = axis_taps(w)
+    rows = f[:, r0, :] * (1 - ry)[None, :, None] + f[:, r1, :] * ry[None, :, None]
+    return rows[:, :, c0] * (1 - rx)[None, None, :] + rows[:, :, c1] * rx[None, None, :]
+
+
+def _bilinear_taps(flow):
+    h, w = flow.shape[1:]
+    yy, xx = np.meshgrid(np.arange(h, dtype=np.float64), np.arange(w, dtype=np.float64),
+                         indexing="ij")
+    sx = xx + flow[0]
+    sy = yy + flow[1]
+    x0, y0 = np.floor(sx), np.floor(sy)
+    return sx, sy, x0.astype(np.int64), y0.astype(np.int64), sx - x0, sy - y0
+
+
+def warp_zero(F, flow):
+    """Backward warp Gamma: out(x) = F(x + flow(x)), bilinear.
+
+    Taps at floor and floor + 1 in each axis; a tap outside the image
+    contributes zero.  F: (C, h, w); flow: (2, h, w), channel 0 = dx.
+    """
+    C, h, w = F.shape
+    _, _, x0, y0, ax, ay = _bilinear_taps(flow)
+    out = np.zeros_like(F, dtype=np.float64)
+    for dy, wy in ((0, 1 - ay), (1, ay)):
+        for dx, wx in ((0, 1 - ax), (1, ax)):
+            xi, yi = x0 + dx, y0 + dy
+            ok = (xi >= 0) & (xi <= w - 1) & (yi >= 0) & (yi <= h - 1)
+            v = F[:, np.clip(yi, 0, h - 1), np.clip(xi, 0, w - 1)]
+            out += np.where(ok, wx * wy, 0.0)[None] * v
+    return out
+
+
+def warp_clamp(F, flow):
+    """Backward warp with tap indices clamped to the image (border value)."""
+    C, h, w = F.shape
+    _, _, x0, y0, ax, ay = _bilinear_taps(flow)
+    out = np.zeros_like(F, dtype=np.float64)
+    for dy, wy in ((0, 1 - ay), (1, ay)):
+        for dx, wx in ((0, 1 - ax), (1, ax)):
+            xi = np.clip(x0 + dx, 0, w - 1)
+            yi = np.clip(y0 + dy, 0, h - 1)
+            out += (wx * wy)[None] * F[:, yi, xi]
+    return out
+
+
+def cost_volume(F1, F2w, radius=4, slope=0.1):
+    """Correlation layer: 81 channels for radius 4.
+
+    CV[k, y, x] = lrelu( (1/C) sum_c F1[c, y, x] * F2w[c, y + dy, x + dx] ),
+    k = (dy + r)(2r + 1) + (dx + r), dy, dx in [-r, r]; a displaced position
+    outside the image gives a zero product.
+    """
+    C, h, w = F1.shape
+    n = 2 * radius + 1
+    cv = np.zeros((n * n, h, w))
+    for dy in range(-radius, radius + 1):
+        for dx in range(-radius, radius + 1):
+            k = (dy + radius) * n + (dx + radius)
+            ys0, ys1 = max(0, -dy), min(h, h - dy)
+            xs0, xs1 = max(0, -dx), min(w, w - dx)
+            if ys0 >= ys1 or xs0 >= xs1:
+                continue
+            a = F1[:, ys0:ys1, xs0:xs1]
+            bb = F2w[:, ys0 + dy:ys1 + dy, xs0 + dx:xs1 + dx]
+            cv[k, ys0:ys1, xs0:xs1] = np.einsum("chw,chw->hw", a, bb) / C
+    return lrelu(cv, slope)
+
+
+# --------------------------------------------------------------------------
+# network
+
+
+def pyramid(img_padded, wts, desc):
+    """Feature pyramid: per level a stride-2 conv then a stride-1 conv, each
+    followed by LeakyReLU.  Returns [F^1, ..., F^L], F^l: (C_l, H/2^l, W/2^l).
+    """
+    slope = desc["leaky"]
+    x = np.asarray(img_padded, np.float64)
+    feats = []
+    for l in range(1, desc["levels"] + 1):
+        x = lrelu(conv3x3(x, *wts[f"pyr{l}a"], stride=2), slope)
+        x = lrelu(conv3x3(x, *wts[f"pyr{l}b"], stride=1), slope)
+        feats.append(x)
+    return feats
+
+
+def decode_level(l, F1, F2, U, wts, desc):
+    """One light flow estimator at level l.
+
+    Warp the second image's features by the upsampled flow U, correlate with
+    the first image's features, and estimate a flow increment from
+    [cost volume | F1 | U] with three conv layers; the head sees the last two
+    layers' outputs [h2 | h3].  Returns flow_l = U + increment.
+    """
+    slope = desc["leaky"]
+    F2w = warp_zero(F2, U)
+    cv = cost_volume(F1, F2w, desc["radius"], slope)
+    z = np.concatenate([cv, F1, U], axis=0)
+    h1 = lrelu(conv3x3(z, *wts[f"dec{l}c1"]), slope)
+    h2 = lrelu(conv3x3(h1, *wts[f"dec{l}c2"]), slope)
+    h3 = lrelu(conv3x3(h2, *wts[f"dec{l}c3"]), slope)
+    delta = conv3x3(np.concatenate([h2, h3], axis=0), *wts[f"dec{l}head"])
+    return U + delta
+
+
+def flow_from_pyramids(P1, P2, wts, desc, out_hw):
+    """Coarse-to-fine flow from image 1 to image 2 given both pyramids.
+
+    U_L = 0; U_l = 2 up2(flow_{l+1}); output crop(2 up2(flow_1)) in pixels of
+    the input resolution, cropped to ``out_hw``.
+    """
+    L = desc["levels"]
+    flow = None
+    for l in range(L, 0, -1):
+        F1, F2 = P1[l - 1], P2[l - 1]
+        U = np.zeros((2,) + F1.shape[1:]) if flow is None else 2.0 * up2(flow)
+        flow = decode_level(l, F1, F2, U, wts, desc)
+    full = 2.0 * up2(flow)
+    H, W = out_hw
+    return full[:, :H, :W]
+
+
+def flow(A, B, wts, desc):
+    """flow_estimate(prev=A, cur=B): flow from A to B on A's grid, (2, H, W)."""
+    A = np.asarray(A, np.float64)
+    B = np.asarray(B, np.float64)
+    L = desc["levels"]
+    PA = pyramid(pad_frame(A, L), wts, desc)
+    PB = pyramid(pad_frame(B, L), wts, desc)
+    return flow_from_pyramids(PA, PB, wts, desc, A.shape[1:])
+
+
+def flow_pair(A, B, wts, desc):
+    """(flow A->B, flow B->A) sharing the two pyramids."""
+    A = np.asarray(A, np.float64)
+    B = np.asarray(B, np.float64)
+    L = desc["levels"]
+    PA = pyramid(pad_frame(A, L), wts, desc)
+    PB = pyramid(pad_frame(B, L), wts, desc)
+    hw = A.shape[1:]
+    return (flow_from_pyramids(PA, PB, wts, desc, hw),
+            flow_from_pyramids(PB, PA, wts, desc, hw))
+
+
+# --------------------------------------------------------------------------
+# consistency step
+
+
+def consistency(P, Oprev, ffw, fbw, alpha):
+    """One consistency step; returns (out, mask, margin, G).
+
+    P = P_t, Oprev = O_{t-1}: (3, H, W); ffw = flow(I_{t-1} -> I_t) and
+    fbw = flow(I_t -> I_{t-1}): (2, H, W); alpha in [0, 1].
+
+    s = x + fbw(x) is where pixel x of frame t came from in frame t-1.
+      G   = bilinear(O_{t-1}, s)      (Eq. 4, Gamma by backward warp)
+      f~  = bilinear(ffw, s)
+      m   = s inside the frame and |fbw + f~|^2 <= 0.01 (|fbw|^2 + |f~|^2) + 0.5
+      w   = alpha * m                 (w_p with the clamp k_1 = alpha)
+      out = (1 - w) P + w G           (Eq. 5 with L_t = P_t)
+    ``margin`` is rhs - lhs of the test (m = inside and margin >= 0).
+    """
+    P = np.asarray(P, np.float64)
+    Oprev = np.asarray(Oprev, np.float64)
+    ffw = np.asarray(ffw, np.float64)
+    fbw = np.asarray(fbw, np.float64)
+    H, W = P.shape[1:]
+    sx, sy, *_ = _bilinear_taps(fbw)
+    inside = (sx >= 0) & (sx <= W - 1) & (sy >= 0) & (sy <= H - 1)
+    G = warp_clamp(Oprev, fbw)
+    ft = warp_clamp(ffw, fbw)
+    lhs = (fbw[0] + ft[0]) ** 2 + (fbw[1] + ft[1]) ** 2
+    rhs = 0.01 * (fbw[0] ** 2 + fbw[1] ** 2 + ft[0] ** 2 + ft[1] ** 2) + 0.5
+    margin = rhs - lhs
+    m = inside & (margin >= 0)
+    w = alpha * m.astype(np.float64)
+    out = (1.0 - w)[None] * P + w[None] * G
+    return out, m, margin, G
+
+
+def run_sequence(I, P, wts, desc, alpha):
+    """O_1 = P_1; O_t = consistency(P_t, O_{t-1}, flow(I_{t-1}, I_t),
+    flow(I_t, I_{t-1}), alpha).  Returns the list of O_t."""
+    outs = [np.asarray(P[0], np.float64)]
+    for t in range(1, len(I)):
+        ffw, fbw = flow_pair(I[t - 1], I[t], wts, desc)
+        outs.append(consistency(P[t], outs[-1], ffw, fbw, alpha)[0])
+    return outs
+
+
+# --------------------------------------------------------------------------
+# metrics
+
+
+def epe(a, b):
+    """Mean end-point error over pixels (supplementary Eq. S1): mean |a - b|_2."""
+    d = np.asarray(a, np.float64) - np.asarray(b, np.float64)
+    return float(np.mean(np.sqrt(d[0] ** 2 + d[1] ** 2)))
+
+
+def warping_error(Vt, Vt1, flow_t_t1, mask):
+    """Eq. 9: sum_i M_i |V_t - warp(V_{t+1})|_1 / sum_i M_i, with the warp a
+    backward bilinear warp of V_{t+1} by the flow from t to t+1."""
+    Vh = warp_clamp(np.asarray(Vt1, np.float64), np.asarray(flow_t_t1, np.float64))
+    d = np.abs(np.asarray(Vt, np.float64) - Vh).sum(axis=0)
+    M = np.asarray(mask, np.float64)
+    return float((M * d).sum() / M.sum())

@@ -1,0 +1,428 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test ties one oracle function to a closed form, a brute-force loop, a
+library routine used only here, or an exact invariant of the method, so that a
+dropped term, a wrong sign or index, or a transposed operand fails somewhere.
+CPU only.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as Fnn
+
+from oracle import tcflow_oracle as O
+from paper_2301_00750_amd import synth
+
+RNG = np.random.default_rng(1234)
+
+
+def rand(*shape):
+    return RNG.standard_normal(shape)
+
+
+# ---------------------------------------------------------------- pad / lrelu
+
+
+def test_pad_frame_edge_replicate():
+    img = rand(3, 13, 21)
+    p = O.pad_frame(img, 3)
+    assert p.shape == (3, 16, 24)
+    assert np.array_equal(p[:, :13, :21], img)
+    for i in range(13, 16):
+        assert np.array_equal(p[:, i, :21], img[:, 12, :])
+    for j in range(21, 24):
+        assert np.array_equal(p[:, :13, j], img[:, :, 20])
+    assert np.all(p[:, 13:, 21:] == img[:, 12:13, 20:21])
+    # already a multiple: unchanged
+    assert np.array_equal(O.pad_frame(img[:, :8, :16], 3), img[:, :8, :16])
+
+
+def test_lrelu_closed_form():
+    z = np.array([-2.0, -0.5, 0.0, 0.25, 3.0])
+    assert np.array_equal(O.lrelu(z, 0.1), np.array([-0.2, -0.05, 0.0, 0.25, 3.0]))
+
+
+# ---------------------------------------------------------------- conv
+
+
+def conv_brute(x, w, b, s):
+    cin, H, W = x.shape
+    co = w.shape[0]
+    Ho, Wo = (H - 1) // s + 1, (W - 1) // s + 1
+    y = np.zeros((co, Ho, Wo))
+    for o in range(co):
+        for i in range(Ho):
+            for j in range(Wo):
+                acc = b[o]
+                for c in range(cin):
+                    for p in range(3):
+                        for q in range(3):
+                            yy, xx = s * i + p - 1, s * j + q - 1
+                            if 0 <= yy < H and 0 <= xx < W:
+                                acc += w[o, c, p, q] * x[c, yy, xx]
+                y[o, i, j] = acc
+    return y
+
+
+@pytest.mark.parametrize("stride,H,W", [(1, 5, 7), (2, 6, 8), (2, 7, 5), (1, 1, 1), (2, 1, 2)])
+def test_conv_vs_brute_force(stride, H, W):
+    x, w, b = rand(3, H, W), rand(4, 3, 3, 3), rand(4)
+    assert np.allclose(O.conv3x3(x, w, b, stride), conv_brute(x, w, b, stride),
+                       rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("stride", [1, 2])
+def test_conv_vs_torch_conv2d(stride):
+    x, w, b = rand(19, 24, 30), rand(11, 19, 3, 3), rand(11)
+    ref = Fnn.conv2d(torch.from_numpy(x)[None], torch.from_numpy(w), torch.from_numpy(b),
+                     stride=stride, padding=1)[0].numpy()
+    # a tiny band forces several im2col bands and a ragged last band
+    got = O.conv3x3(x, w, b, stride, band_bytes=19 * 9 * 30 * 8 * 5)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-11)
+
+
+# ---------------------------------------------------------------- up2
+
+
+def test_up2_vs_interpolate():
+    f = rand(2, 5, 7)
+    ref = Fnn.interpolate(torch.from_numpy(f)[None], scale_factor=2, mode="bilinear",
+                          align_corners=False)[0].numpy()
+    assert np.allclose(O.up2(f), ref, rtol=0, atol=1e-13)
+
+
+def test_up2_closed_form_interior():
+    f = rand(1, 4, 6)
+    u = O.up2(f)
+    # interior columns of row 0 (rows are clamped at the top edge):
+    for i in range(1, 5):
+        assert u[0, 0, 2 * i] == 0.25 * f[0, 0, i - 1] + 0.75 * f[0, 0, i]
+        assert u[0, 0, 2 * i + 1] == 0.75 * f[0, 0, i] + 0.25 * f[0, 0, i + 1]
+    assert u[0, 0, 0] == f[0, 0, 0] and u[0, 0, 11] == f[0, 0, 5]
+    # a constant field stays constant
+    assert np.all(O.up2(np.full((2, 3, 3), 1.5)) == 1.5)
+
+
+# ---------------------------------------------------------------- warps
+
+
+def test_warp_zero_flow_is_identity():
+    F = rand(5, 9, 11)
+    assert np.array_equal(O.warp_zero(F, np.zeros((2, 9, 11))), F)
+    assert np.array_equal(O.warp_clamp(F, np.zeros((2, 9, 11))), F)
+
+
+@pytest.mark.parametrize("dx,dy", [(3, -2), (-1, 4), (0, 1)])
+def test_warp_integer_shift_exact(dx, dy):
+    C, h, w = 4, 10, 12
+    F = rand(C, h, w)
+    fl = np.zeros((2, h, w))
+    fl[0], fl[1] = dx, dy
+    got = O.warp_zero(F, fl)
+    for y in range(h):
+        for x in range(w):
+            sy, sx = y + dy, x + dx
+            if 0 <= sy < h and 0 <= sx < w:
+                assert np.array_equal(got[:, y, x], F[:, sy, sx])
+            else:
+                assert np.all(got[:, y, x] == 0)
+
+
+def _grid(flow):
+    h, w = flow.shape[1:]
+    yy, xx = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    gx = 2 * (xx + flow[0]) / (w - 1) - 1
+    gy = 2 * (yy + flow[1]) / (h - 1) - 1
+    return torch.from_numpy(np.stack([gx, gy], -1))[None]
+
+
+@pytest.mark.parametrize("mode,fn", [("zeros", O.warp_zero), ("border", O.warp_clamp)])
+def test_warp_vs_grid_sample(mode, fn):
+    C, h, w = 3, 9, 13
+    F = rand(C, h, w)
+    fl = 3.0 * rand(2, h, w)
+    ref = Fnn.grid_sample(torch.from_numpy(F)[None], _grid(fl), mode="bilinear",
+                          padding_mode=mode, align_corners=True)[0].numpy()
+    assert np.allclose(fn(F, fl), ref, rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- cost volume
+
+
+def cv_brute(F1, F2, r, slope):
+    C, h, w = F1.shape
+    n = 2 * r + 1
+    out = np.zeros((n * n, h, w))
+    for y, x in itertools.product(range(h), range(w)):
+        for dy in range(-r, r + 1):
+            for dx in range(-r, r + 1):
+                k = (dy + r) * n + dx + r
+                yy, xx = y + dy, x + dx
+                s = 0.0
+                if 0 <= yy < h and 0 <= xx < w:
+                    for c in range(C):
+                        s += F1[c, y, x] * F2[c, yy, xx]
+                s /= C
+                out[k, y, x] = s if s >= 0 else slope * s
+    return out
+
+
+def test_cost_volume_vs_brute_force():
+    F1, F2 = rand(5, 7, 9), rand(5, 7, 9)
+    assert np.allclose(O.cost_volume(F1, F2, 4, 0.1), cv_brute(F1, F2, 4, 0.1), atol=1e-13)
+    assert np.allclose(O.cost_volume(F1, F2, 2, 0.1), cv_brute(F1, F2, 2, 0.1), atol=1e-13)
+
+
+def test_cost_volume_self_centre_channel():
+    F1 = rand(6, 8, 8)
+    cv = O.cost_volume(F1, F1, 4, 0.1)
+    assert np.allclose(cv[40], (F1 ** 2).mean(0), rtol=1e-14)
+    assert np.all(cv[40] >= 0)
+
+
+# ---------------------------------------------------------------- mask / blend
+
+
+def _consistency_inputs(h=12, w=16):
+    P, Op = RNG.random((3, h, w)), RNG.random((3, h, w))
+    return P, Op
+
+
+def test_mask_zero_flows_all_visible():
+    P, Op = _consistency_inputs()
+    z = np.zeros((2,) + P.shape[1:])
+    out, m, margin, G = O.consistency(P, Op, z, z, 0.5)
+    assert m.all()
+    assert np.array_equal(G, Op)
+
+
+def test_mask_consistent_shift_count():
+    h, w = 12, 16
+    P, Op = _consistency_inputs(h, w)
+    ffw = np.zeros((2, h, w)); ffw[0], ffw[1] = 3, -2
+    fbw = -ffw
+    _, m, margin, _ = O.consistency(P, Op, ffw, fbw, 1.0)
+    assert m.sum() == (w - 3) * (h - 2)
+    yy, xx = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    assert np.array_equal(m, (xx >= 3) & (yy <= h - 3))
+
+
+def test_mask_inconsistent_all_occluded():
+    h, w = 12, 16
+    P, Op = _consistency_inputs(h, w)
+    f = np.zeros((2, h, w)); f[0] = 5.0
+    out, m, margin, _ = O.consistency(P, Op, f, f, 1.0)
+    assert not m.any()
+    # inside pixels: lhs = 100, rhs = 0.01 * 50 + 0.5 = 1
+    assert np.allclose(margin, -99.0)
+    assert np.array_equal(out, P)
+
+
+def test_mask_threshold_both_norms():
+    # fbw = (1, 0) at every pixel, ffw = (-0.3, 0): lhs = 0.49,
+    # rhs = 0.01 * (1 + 0.09) + 0.5 = 0.5109 -> visible; with only |fbw|^2 on
+    # the right it would still be visible, so also check a case that separates
+    # the readings: fbw = (0, 0), ffw = (0.7075, 0): lhs = 0.50056,
+    # rhs(both) = 0.505006 -> visible, rhs(fbw only) = 0.5 -> occluded.
+    h, w = 6, 8
+    P, Op = _consistency_inputs(h, w)
+    fbw = np.zeros((2, h, w))
+    ffw = np.zeros((2, h, w)); ffw[0] = 0.7075
+    _, m, margin, _ = O.consistency(P, Op, ffw, fbw, 1.0)
+    assert m.all()
+    assert np.allclose(margin, 0.01 * 0.7075 ** 2 + 0.5 - 0.7075 ** 2)
+
+
+def test_blend_endpoints_bitwise():
+    h, w = 12, 16
+    P, Op = _consistency_inputs(h, w)
+    ffw = 2.0 * RNG.standard_normal((2, h, w))
+    fbw = -ffw + 0.3 * RNG.standard_normal((2, h, w))
+    out0, m, _, G = O.consistency(P, Op, ffw, fbw, 0.0)
+    assert np.array_equal(out0, P)
+    out1, m1, _, G1 = O.consistency(P, Op, ffw, fbw, 1.0)
+    assert m1.any() and (~m1).any()
+    assert np.array_equal(out1[:, m1], G1[:, m1])
+    assert np.array_equal(out1[:, ~m1], P[:, ~m1])
+    # P == G: the blend returns P up to rounding for every alpha
+    outp, mp, _, Gp = O.consistency(G1, Op, ffw, fbw, 0.37)
+    assert np.allclose(outp, G1, rtol=0, atol=1e-15)
+    # linear in alpha where visible
+    outh, _, _, _ = O.consistency(P, Op, ffw, fbw, 0.25)
+    assert np.allclose(outh, 0.75 * P + 0.25 * np.where(m1[None], G1, P), atol=1e-15)
+
+
+def test_consistency_warp_direction():
+    """With exact flows of an integer translation, warping O_{t-1} = I_{t-1}
+    by the backward flow reproduces I_t wherever the source is inside."""
+    prev, cur, gfw, gbw = synth.tiny_pair()
+    prev, cur = prev.numpy().astype(np.float64), cur.numpy().astype(np.float64)
+    h, w = prev.shape[1:]
+    out, m, _, G = O.consistency(cur, prev, gfw.numpy(), gbw.numpy(), 1.0)
+    assert m.sum() == (w - 3) * (h - 2)
+    assert np.array_equal(G[:, m], cur[:, m])
+    assert np.array_equal(out, cur)
+
+
+# ---------------------------------------------------------------- network structure
+
+
+def _zero_weights(desc):
+    blob = synth.he_weights(desc)
+    return {k: (np.zeros_like(w), np.zeros_like(b)) for k, (w, b) in O.unpack_weights(blob, desc).items()}
+
+
+def test_unpack_weights_layout():
+    d = synth.load_desc("tiny")
+    blob = synth.he_weights(d)
+    wts = O.unpack_weights(blob, d)
+    assert blob.size == synth.blob_floats(d)
+    assert wts["pyr1a"][0].shape == (16, 3, 3, 3)
+    assert wts["dec4c1"][0].shape == (96, 81 + 96 + 2, 3, 3)
+    assert wts["dec2head"][0].shape == (2, 96, 3, 3)
+    # first and last float land where the layout says
+    assert wts["pyr1a"][0][0, 0, 0, 0] == blob[0]
+    assert wts["dec4head"][1][-1] == blob[-1]
+    with pytest.raises(ValueError):
+        O.unpack_weights(blob[:-1], d)
+
+
+def test_level_recursion_closed_form():
+    """Zero weights and a head bias b at every level: flow_L = b,
+    flow_l = 2 up2(flow_{l+1}) + b = (2^(L-l+1) - 1) b, output 2 (2^L - 1) b."""
+    d = synth.load_desc("tiny")
+    wts = _zero_weights(d)
+    b = np.array([0.5, -0.25])
+    for l in range(1, d["levels"] + 1):
+        wts[f"dec{l}head"] = (wts[f"dec{l}head"][0], b.copy())
+    A = RNG.random((3, 45, 70))  # not a multiple of 16: pads and crops
+    f = O.flow(A, A, wts, d)
+    assert f.shape == (2, 45, 70)
+    L = d["levels"]
+    assert np.all(f[0] == 2 * (2 ** L - 1) * 0.5)
+    assert np.all(f[1] == 2 * (2 ** L - 1) * -0.25)
+
+
+def _selector_decoder(d, wts, l, src_channel, tap=(1, 1)):
+    """Decoder of level l that outputs Delta_u = lrelu^3(Z[src_channel]) read
+    through one tap of c1; c2 and c3 copy channel 0 through their centre tap
+    and the head reads h3's channel 0, the first channel after h2."""
+    w1, b1 = wts[f"dec{l}c1"]
+    w1 = np.zeros_like(w1); w1[0, src_channel, tap[0], tap[1]] = 1.0
+    w2 = np.zeros_like(wts[f"dec{l}c2"][0]); w2[0, 0, 1, 1] = 1.0
+    w3 = np.zeros_like(wts[f"dec{l}c3"][0]); w3[0, 0, 1, 1] = 1.0
+    wh = np.zeros_like(wts[f"dec{l}head"][0]); wh[0, d["dec"][1], 1, 1] = 1.0
+    wts[f"dec{l}c1"] = (w1, np.zeros_like(b1))
+    wts[f"dec{l}c2"] = (w2, np.zeros(w2.shape[0]))
+    wts[f"dec{l}c3"] = (w3, np.zeros(w3.shape[0]))
+    wts[f"dec{l}head"] = (wh, np.zeros(2))
+
+
+def _l3(z):
+    return np.where(z >= 0, z, 1e-3 * z)
+
+
+@pytest.mark.parametrize("which", ["cv_centre", "cv_offset", "f1", "u_v", "tap"])
+def test_decoder_channel_order(which):
+    d = synth.load_desc("tiny")
+    wts = _zero_weights(d)
+    l, C = 2, d["ch"][1]
+    h, w = 6, 8
+    F1, F2 = rand(C, h, w), rand(C, h, w)
+    U = rand(2, h, w)
+    cv = cv_brute(F1, O.warp_zero(F2, U), 4, 0.1)
+    if which == "cv_centre":
+        ch, exp = 40, cv[40]
+    elif which == "cv_offset":
+        k = (-1 + 4) * 9 + (2 + 4)  # dy = -1, dx = +2
+        ch, exp = k, cv[k]
+    elif which == "f1":
+        ch, exp = 81 + 5, F1[5]
+    elif which == "u_v":
+        ch, exp = 81 + C + 1, U[1]
+    else:
+        ch = 81 + 3
+        exp = np.zeros((h, w))
+        exp[1:, :-1] = F1[3, :-1, 1:]  # tap (0, 2): input at (y - 1, x + 1)
+    tap = (0, 2) if which == "tap" else (1, 1)
+    _selector_decoder(d, wts, l, ch, tap)
+    got = O.decode_level(l, F1, F2, U, wts, d) - U
+    assert np.allclose(got[0], _l3(exp), atol=1e-12)
+    assert np.all(got[1] == 0)
+
+
+def test_flow_pair_equals_two_flows_and_is_deterministic():
+    d = synth.load_desc("tiny")
+    wts = O.unpack_weights(synth.he_weights(d), d)
+    A, B = RNG.random((3, 32, 48)), RNG.random((3, 32, 48))
+    fw, bw = O.flow_pair(A, B, wts, d)
+    assert np.array_equal(fw, O.flow(A, B, wts, d))
+    assert np.array_equal(bw, O.flow(B, A, wts, d))
+    fw2, _ = O.flow_pair(A, B, wts, d)
+    assert np.array_equal(fw, fw2)
+
+
+# ---------------------------------------------------------------- sequence / metrics
+
+
+def test_sequence_first_frame_and_epe():
+    d = synth.load_desc("tiny")
+    wts = O.unpack_weights(synth.he_weights(d), d)
+    I = [RNG.random((3, 16, 16)) for _ in range(3)]
+    P = [RNG.random((3, 16, 16)) for _ in range(3)]
+    outs = O.run_sequence(I, P, wts, d, 0.5)
+    assert len(outs) == 3 and np.array_equal(outs[0], P[0])
+    a = RNG.random((2, 4, 5))
+    b = a.copy(); b[0] += 3.0; b[1] -= 4.0
+    assert np.isclose(O.epe(a, b), 5.0)
+
+
+def test_warping_error_nonincreasing_in_alpha():
+    """Exact flows of an integer shift: E_warp(O_1, O_2) over the visible set
+    scales with (1 - alpha)."""
+    prev, cur, gfw, gbw = synth.tiny_pair()
+    prev, cur = prev.numpy().astype(np.float64), cur.numpy().astype(np.float64)
+    gfw, gbw = gfw.numpy().astype(np.float64), gbw.numpy().astype(np.float64)
+    P1, P2 = synth.stylize(torch.from_numpy(prev).float(), 0).double().numpy(), \
+        synth.stylize(torch.from_numpy(cur).float(), 1).double().numpy()
+    h, w = prev.shape[1:]
+    yy, xx = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    M = (xx + 3 <= w - 1) & (yy - 2 >= 0)  # fw target inside
+    errs = []
+    for a in (0.0, 0.25, 0.5, 0.75, 1.0):
+        O2 = O.consistency(P2, P1, gfw, gbw, a)[0]
+        errs.append(O.warping_error(P1, O2, gfw, M))
+    assert all(e1 >= e2 for e1, e2 in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-15
+    assert np.allclose(errs, [(1 - a) * errs[0] for a in (0.0, 0.25, 0.5, 0.75, 1.0)], rtol=1e-12)
+
+
+def test_pyramid_structure_selector():
+    """Pyramid convs that copy channel 0 through one tap: level l samples the
+    padded input at stride 2^l, and every conv is followed by LeakyReLU."""
+    d = synth.load_desc("tiny")
+    wts = _zero_weights(d)
+    for l in range(1, d["levels"] + 1):
+        wa = np.zeros_like(wts[f"pyr{l}a"][0]); wa[0, 0, 1, 1] = 1.0
+        wb = np.zeros_like(wts[f"pyr{l}b"][0]); wb[0, 0, 1, 1] = 1.0
+        wts[f"pyr{l}a"] = (wa, np.zeros(wa.shape[0]))
+        wts[f"pyr{l}b"] = (wb, np.zeros(wb.shape[0]))
+    img = RNG.standard_normal((3, 32, 48))
+    feats = O.pyramid(img, wts, d)
+    for l, F in enumerate(feats, start=1):
+        s = 2 ** l
+        assert F.shape == (d["ch"][l - 1], 32 // s, 48 // s)
+        z = img[0, ::s, ::s]
+        # 2 LeakyReLUs per level: negative values shrink by 0.01 per level
+        exp = np.where(z >= 0, z, (0.01 ** l) * z)
+        assert np.allclose(F[0], exp, rtol=1e-14, atol=0)
+        assert np.all(F[1:] == 0)
+    # stride-2 tap (0, 0) reads input (2i - 1, 2j - 1), zero outside
+    wa = np.zeros_like(wts["pyr1a"][0]); wa[0, 0, 0, 0] = 1.0
+    wts["pyr1a"] = (wa, np.zeros(wa.shape[0]))
+    F1 = O.pyramid(np.abs(img), wts, d)[0]
+    exp = np.zeros((16, 24))
+    exp[1:, 1:] = np.abs(img)[0, 1:-2:2, 1:-2:2]
+    assert np.array_equal(F1[0], exp)
