@@ -1,0 +1,142 @@
+/*
+ * tcflow.h -- C ABI of the per-frame hot path of streaming temporal
+ * consistency ("Interactive Control over Temporal Consistency while
+ * Stylizing Video Streams"): a lite coarse-to-fine optical-flow network
+ * followed by the consistency step, as HIP kernels for gfx950 (MI355X).
+ *
+ * Conventions shared by every call
+ *   - Every tensor pointer is HIP device memory owned by the caller, dense,
+ *     float32, row major.  Frames are NCHW n x 3 x h x w, RGB in [0, 1].
+ *     Flows are n x 2 x h x w in pixels: channel 0 = dx, channel 1 = dy,
+ *     on the grid of the first frame of the pair.
+ *   - Workspaces and pyramid buffers are caller-owned device memory of at
+ *     least the size the matching *_bytes query returns, 256-byte aligned.
+ *     The library never allocates on a call path and never frees caller
+ *     memory.  Outputs must not alias inputs (except where stated).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is only
+ *     enqueued; nothing synchronises the host.  Argument, shape and
+ *     workspace errors are returned before anything is enqueued; a kernel
+ *     launch error returns TC_ERR_HIP; faults during execution surface at the
+ *     caller's next synchronisation.  Non-finite pixel values propagate and
+ *     are not checked.  No C++ exception crosses this boundary.
+ *   - A tc_net is immutable after creation: calls on different streams with
+ *     distinct workspaces may run concurrently.
+ */
+#ifndef TCFLOW_H
+#define TCFLOW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TC_API __attribute__((visibility("default")))
+
+typedef enum {
+  TC_OK = 0,
+  TC_ERR_INVALID_ARG = 1, /* null pointer, n/h/w <= 0, alpha outside [0,1] or NaN */
+  TC_ERR_SHAPE = 2,       /* descriptor or weight count inconsistent           */
+  TC_ERR_WORKSPACE = 3,   /* workspace / pyramid buffer too small or unaligned */
+  TC_ERR_UNSUPPORTED = 4, /* precision or size this build does not handle      */
+  TC_ERR_HIP = 5          /* a HIP runtime call or kernel launch failed        */
+} tc_status;
+
+typedef enum { TC_FP32 = 0, TC_BF16 = 1, TC_FP8_E4M3 = 2 } tc_precision;
+
+/* Network descriptor.  levels L in [1, 8]; ch[l-1] = channels of pyramid
+ * level l (multiples of 8, at most 128); dec = widths of the three decoder
+ * conv layers (multiples of 16, at most 128); radius = cost-volume radius
+ * (4 gives 81 displacements); leaky = LeakyReLU slope. */
+typedef struct {
+  int levels;
+  int ch[8];
+  int dec[3];
+  int radius;
+  float leaky;
+} tc_net_desc;
+
+typedef struct tc_net tc_net; /* opaque */
+
+TC_API const char* tc_status_str(int status);
+TC_API const char* tc_version(void);
+
+/* Number of float32 values of the weight blob for `desc`.  Blob layout,
+ * layer after layer: W[cout][cin][3][3] then b[cout]; order: pyramid convs
+ * of level 1..L (stride 2: C_{l-1} -> C_l with C_0 = 3, then stride 1:
+ * C_l -> C_l), then the decoders of level 1..L: c1 ((2r+1)^2 + C_l + 2 ->
+ * dec0), c2 (dec0 -> dec1), c3 (dec1 -> dec2), head (dec1 + dec2 -> 2). */
+TC_API size_t tc_weight_floats(const tc_net_desc* desc);
+
+/* Copies the host weight blob to the current HIP device, packed for the
+ * kernels of `precision`.  Paper, Sec. 3.2: PWC-Net-shaped network with
+ * light estimators (a conv feature pyramid, warping, correlation and a CNN
+ * flow estimator per level).  *out is set only on TC_OK. */
+TC_API int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_floats,
+                         int precision, tc_net** out);
+TC_API void tc_net_destroy(tc_net* net);
+
+/* ---- feature pyramids (cacheable per frame) ---------------------------- */
+
+/* Bytes of the buffer that holds the feature pyramid of n frames of h x w
+ * (levels at resolution ceil-to-2^L / 2^l, NHWC) plus its build scratch. */
+TC_API size_t tc_pyramid_bytes(const tc_net* net, int n, int h, int w);
+
+/* Feature pyramid of `frames` (n x 3 x h x w): the frame is edge-replicated
+ * up to a multiple of 2^L, then each level applies a stride-2 and a stride-1
+ * 3x3 conv, each followed by LeakyReLU.  Writes into `pyr`. */
+TC_API int tc_pyramid(const tc_net* net, const float* frames, int n, int h, int w, void* pyr,
+                      size_t pyr_bytes, void* stream);
+
+/* ---- flow -------------------------------------------------------------- */
+
+/* Scratch bytes of tc_flow_from_pyramids for n pairs (both directions). */
+TC_API size_t tc_decoder_workspace_bytes(const tc_net* net, int n, int h, int w);
+
+/* Coarse-to-fine flow from the frames of pyramid `pyr1` to those of `pyr2`
+ * (flow12, n x 2 x h x w) and, if flow21 is not NULL, the opposite direction
+ * in the same batched pass.  Per level l = L..1: U = 2 up2(flow_{l+1})
+ * (U_L = 0), warp the second pyramid's features by U, 81-channel cost
+ * volume, light estimator on [cost volume | F1 | U] -> increment,
+ * flow_l = U + increment; output = 2 up2(flow_1) cropped to h x w.  Paper,
+ * Sec. 3.2 and supplementary S1. */
+TC_API int tc_flow_from_pyramids(const tc_net* net, const void* pyr1, const void* pyr2, int n,
+                                 int h, int w, float* flow12, float* flow21, void* ws,
+                                 size_t ws_bytes, void* stream);
+
+/* Scratch bytes of tc_flow_estimate / tc_flow_estimate_pair (two pyramids
+ * plus the decoder scratch). */
+TC_API size_t tc_flow_workspace_bytes(const tc_net* net, int n, int h, int w);
+
+/* flow_estimate(prev, cur) -> flow from prev to cur on prev's grid. */
+TC_API int tc_flow_estimate(const tc_net* net, const float* prev, const float* cur, int n, int h,
+                            int w, float* flow, void* ws, size_t ws_bytes, void* stream);
+
+/* flow_fw = flow(prev -> cur), flow_bw = flow(cur -> prev), sharing both
+ * pyramids and one batched decoder pass. */
+TC_API int tc_flow_estimate_pair(const tc_net* net, const float* prev, const float* cur, int n,
+                                 int h, int w, float* flow_fw, float* flow_bw, void* ws,
+                                 size_t ws_bytes, void* stream);
+
+/* ---- consistency step -------------------------------------------------- */
+
+/* out_t from stylized P_t, previous output O_{t-1}, flow_fw = flow(I_{t-1}
+ * -> I_t) and flow_bw = flow(I_t -> I_{t-1}) (paper Sec. 3.1, Eq. 4 and
+ * Eq. 5; non-occlusion mask of Sec. 5, Eq. 9).  Per pixel x:
+ *   s   = x + flow_bw(x)
+ *   G   = bilinear(prev_out, s),  f~ = bilinear(flow_fw, s)
+ *   m   = s inside the frame and
+ *         |flow_bw + f~|^2 <= 0.01 (|flow_bw|^2 + |f~|^2) + 0.5
+ *   w   = alpha * m
+ *   out = (1 - w) * stylized + w * G
+ * alpha in [0, 1]: 0 returns stylized exactly, 1 returns G where visible.
+ * `out` may alias `stylized`; mask_or_null (n x h x w bytes, 1 = visible)
+ * is written when not NULL.  For t = 1 the caller sets O_1 = P_1. */
+TC_API int tc_consistency_step(const float* stylized, const float* prev_out, const float* flow_fw,
+                               const float* flow_bw, float alpha, int n, int h, int w, float* out,
+                               unsigned char* mask_or_null, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TCFLOW_H */

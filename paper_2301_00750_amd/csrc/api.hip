@@ -1,0 +1,471 @@
+// C ABI of libtcflow: argument checking, weight packing, buffer layouts and
+// the launch sequence of the flow network and the consistency step.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/tcflow.h"
+#include "tc_internal.h"
+
+using namespace tc;
+
+struct tc_net {
+  tc_net_desc d;
+  int precision;
+  int ncv;          // (2r+1)^2
+  int zcb;          // blocks of the cost-volume buffer (ncv + 2, rounded up to 8)
+  ConvLayer pyr[8][2];
+  ConvLayer dec[8][4];
+  void* dmem;
+};
+
+namespace {
+
+constexpr int kMaxN = 4096, kMaxHW = 16384;
+constexpr size_t kAlign = 256;
+
+#define TC_TRY_HIP(x)                        \
+  do {                                       \
+    if ((x) != hipSuccess) return TC_ERR_HIP; \
+  } while (0)
+
+bool desc_ok(const tc_net_desc* d) {
+  if (!d || d->levels < 1 || d->levels > 8) return false;
+  for (int l = 0; l < d->levels; ++l)
+    if (d->ch[l] <= 0 || d->ch[l] % 8 || d->ch[l] > 128) return false;
+  for (int i = 0; i < 3; ++i)
+    if (d->dec[i] <= 0 || d->dec[i] % 16 || d->dec[i] > 128) return false;
+  if ((d->dec[1] + d->dec[2]) % 8) return false;
+  if (d->radius != 4) return false;
+  if (!(d->leaky >= 0.f && d->leaky <= 1.f)) return false;
+  return true;
+}
+
+size_t conv_floats(int co, int ci) { return (size_t)co * ci * 9 + co; }
+
+struct LevelDims {
+  int hp, wp;             // padded input size
+  int h[9], w[9];         // level sizes, index l = 1..L
+};
+
+LevelDims dims(const tc_net_desc& d, int h, int w) {
+  LevelDims r;
+  const int m = 1 << d.levels;
+  r.hp = (h + m - 1) / m * m;
+  r.wp = (w + m - 1) / m * m;
+  for (int l = 1; l <= d.levels; ++l) {
+    r.h[l] = r.hp >> l;
+    r.w[l] = r.wp >> l;
+  }
+  return r;
+}
+
+bool shape_ok(int n, int h, int w) {
+  return n > 0 && h > 0 && w > 0 && n <= kMaxN && h <= kMaxHW && w <= kMaxHW;
+}
+
+// ---- pyramid buffer layout: levels 1..L (blocked B = 8), then the staged
+// frame (B = 4) and the scratch for each level's first conv.
+struct PyrLayout {
+  size_t off[9];
+  size_t stage, tmp, total;
+};
+
+PyrLayout pyr_layout(const tc_net_desc& d, int n, int h, int w) {
+  PyrLayout p;
+  LevelDims g = dims(d, h, w);
+  size_t pos = 0, tmp = 0;
+  for (int l = 1; l <= d.levels; ++l) {
+    const size_t bytes = (size_t)n * d.ch[l - 1] * g.h[l] * g.w[l] * sizeof(float);
+    p.off[l] = pos;
+    pos = align_up(pos + bytes, kAlign);
+    if (bytes > tmp) tmp = bytes;
+  }
+  p.stage = pos;
+  pos = align_up(pos + (size_t)n * g.hp * g.wp * 4 * sizeof(float), kAlign);
+  p.tmp = pos;
+  pos = align_up(pos + tmp, kAlign);
+  p.total = pos;
+  return p;
+}
+
+// ---- decoder scratch for a batch of nb images (n pairs -> nb = 2n)
+struct DecLayout {
+  size_t flow[2], U, Z, H1, H23, total;
+};
+
+DecLayout dec_layout(const tc_net* net, int nb, int h, int w) {
+  DecLayout L;
+  LevelDims g = dims(net->d, h, w);
+  const size_t px = (size_t)nb * g.h[1] * g.w[1];
+  size_t pos = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = pos;
+    pos = align_up(pos + bytes, kAlign);
+    return o;
+  };
+  L.flow[0] = take(px * 2 * sizeof(float));
+  L.flow[1] = take(px * 2 * sizeof(float));
+  L.U = take(px * 2 * sizeof(float));
+  L.Z = take(px * net->zcb * 8 * sizeof(float));
+  L.H1 = take(px * net->d.dec[0] * sizeof(float));
+  L.H23 = take(px * (net->d.dec[1] + net->d.dec[2]) * sizeof(float));
+  L.total = pos;
+  return L;
+}
+
+// Pack W[cout][cin][3][3] (host, float) into [cin_pad/kc][9][kc][np] with the
+// given map from packed input channel to source channel (-1 = zero).
+void pack_conv(const float* W, const float* b, int cout, int cin, int kc, int cin_pad,
+               const std::vector<int>& cmap, std::vector<float>& wout, std::vector<float>& bout,
+               int& np) {
+  np = (cout + 15) / 16 * 16;
+  wout.assign((size_t)cin_pad * 9 * np, 0.f);
+  bout.assign(np, 0.f);
+  for (int g = 0; g < cin_pad; ++g) {
+    const int c = cmap[g];
+    if (c < 0) continue;
+    const int chunk = g / kc, kk = g % kc;
+    for (int tap = 0; tap < 9; ++tap)
+      for (int o = 0; o < cout; ++o)
+        wout[(((size_t)chunk * 9 + tap) * kc + kk) * np + o] = W[((size_t)o * cin + c) * 9 + tap];
+  }
+  for (int o = 0; o < cout; ++o) bout[o] = b[o];
+}
+
+View plain_view(const float* p, int cbt, int cb0 = 0) {
+  View v;
+  v.a = p;
+  v.b = p;
+  v.nsplit = 1 << 30;
+  v.cbt = cbt;
+  v.cb0 = cb0;
+  return v;
+}
+
+int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, int in_h, int in_w,
+               float* out, int out_cbt, int out_cb0, int compact, const float* add, int out_h,
+               int out_w, int relu, float slope, int n, int stride, hipStream_t s) {
+  ConvArgs a;
+  a.in0 = in0;
+  a.in1 = in1;
+  a.nb0 = nb0;
+  a.in_h = in_h;
+  a.in_w = in_w;
+  a.out = out;
+  a.out_cbt = out_cbt;
+  a.out_cb0 = out_cb0;
+  a.compact = compact;
+  a.add = add;
+  a.out_h = out_h;
+  a.out_w = out_w;
+  a.w = L.w;
+  a.b = L.b;
+  a.nchunks = L.cin_pad / L.kc;
+  a.cout = L.cout;
+  a.np = L.np;
+  a.lrelu = relu;
+  a.slope = slope;
+  a.n = n;
+  return launch_conv3x3(a, stride, L.kc, s) == hipSuccess ? TC_OK : TC_ERR_HIP;
+}
+
+int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, char* pyr,
+                hipStream_t s) {
+  const tc_net_desc& d = net->d;
+  const LevelDims g = dims(d, h, w);
+  const PyrLayout p = pyr_layout(d, n, h, w);
+  float* stage = reinterpret_cast<float*>(pyr + p.stage);
+  float* tmp = reinterpret_cast<float*>(pyr + p.tmp);
+  TC_TRY_HIP(launch_stage(frames, n, h, w, stage, g.hp, g.wp, s));
+  const float* in = stage;
+  int in_cbt = 1, in_h = g.hp, in_w = g.wp;
+  for (int l = 1; l <= d.levels; ++l) {
+    const int C = d.ch[l - 1];
+    float* feat = reinterpret_cast<float*>(pyr + p.off[l]);
+    int st = conv_layer(net->pyr[l - 1][0], plain_view(in, in_cbt), net->pyr[l - 1][0].cin_pad / net->pyr[l - 1][0].kc,
+                        plain_view(in, in_cbt), in_h, in_w, tmp, C / 8, 0, 0, nullptr, g.h[l], g.w[l],
+                        1, d.leaky, n, 2, s);
+    if (st) return st;
+    st = conv_layer(net->pyr[l - 1][1], plain_view(tmp, C / 8), C / 8, plain_view(tmp, C / 8),
+                    g.h[l], g.w[l], feat, C / 8, 0, 0, nullptr, g.h[l], g.w[l], 1, d.leaky, n, 1, s);
+    if (st) return st;
+    in = feat;
+    in_cbt = C / 8;
+    in_h = g.h[l];
+    in_w = g.w[l];
+  }
+  return TC_OK;
+}
+
+// Decoder pass over nb = n (one direction) or 2n (both) images.
+int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, int h, int w,
+                float* flow12, float* flow21, char* ws, hipStream_t s) {
+  const tc_net_desc& d = net->d;
+  const LevelDims g = dims(d, h, w);
+  const PyrLayout p = pyr_layout(d, n, h, w);
+  const int nb = flow21 ? 2 * n : n;
+  const DecLayout D = dec_layout(net, nb, h, w);
+  float* flows[2] = {reinterpret_cast<float*>(ws + D.flow[0]), reinterpret_cast<float*>(ws + D.flow[1])};
+  float* U = reinterpret_cast<float*>(ws + D.U);
+  float* Z = reinterpret_cast<float*>(ws + D.Z);
+  float* H1 = reinterpret_cast<float*>(ws + D.H1);
+  float* H23 = reinterpret_cast<float*>(ws + D.H23);
+  const int d0b = d.dec[0] / 8, d1b = d.dec[1] / 8, d23b = (d.dec[1] + d.dec[2]) / 8;
+  int cur = 0;
+  for (int l = d.levels; l >= 1; --l) {
+    const int C = d.ch[l - 1], hl = g.h[l], wl = g.w[l];
+    const float* P1 = reinterpret_cast<const float*>(pyr1 + p.off[l]);
+    const float* P2 = reinterpret_cast<const float*>(pyr2 + p.off[l]);
+    View f1, f2;
+    f1.a = P1; f1.b = P2; f1.nsplit = n; f1.cbt = C / 8; f1.cb0 = 0;
+    f2.a = P2; f2.b = P1; f2.nsplit = n; f2.cbt = C / 8; f2.cb0 = 0;
+    const float* Ul = nullptr;
+    if (l < d.levels) {
+      TC_TRY_HIP(launch_up2x2(flows[cur], nb, g.h[l + 1], g.w[l + 1], U, s));
+      Ul = U;
+    }
+    CvArgs cv;
+    cv.f1 = f1;
+    cv.f2 = f2;
+    cv.U = Ul;
+    cv.Z = Z;
+    cv.zcb = net->zcb;
+    cv.n = nb;
+    cv.h = hl;
+    cv.w = wl;
+    cv.C = C;
+    cv.radius = d.radius;
+    cv.slope = d.leaky;
+    TC_TRY_HIP(launch_warp_cost_volume(cv, s));
+    const ConvLayer* L = net->dec[l - 1];
+    int st = conv_layer(L[0], f1, C / 8, plain_view(Z, net->zcb), hl, wl, H1, d0b, 0, 0, nullptr,
+                        hl, wl, 1, d.leaky, nb, 1, s);
+    if (st) return st;
+    st = conv_layer(L[1], plain_view(H1, d0b), d0b, plain_view(H1, d0b), hl, wl, H23, d23b, 0, 0,
+                    nullptr, hl, wl, 1, d.leaky, nb, 1, s);
+    if (st) return st;
+    st = conv_layer(L[2], plain_view(H23, d23b), d1b, plain_view(H23, d23b), hl, wl, H23, d23b,
+                    d1b, 0, nullptr, hl, wl, 1, d.leaky, nb, 1, s);
+    if (st) return st;
+    const int nxt = cur ^ 1;
+    st = conv_layer(L[3], plain_view(H23, d23b), d23b, plain_view(H23, d23b), hl, wl, flows[nxt],
+                    0, 0, 1, Ul, hl, wl, 0, 0.f, nb, 1, s);
+    if (st) return st;
+    cur = nxt;
+  }
+  TC_TRY_HIP(launch_final_flow(flows[cur], nb, g.h[1], g.w[1], flow12, flow21, n, h, w, s));
+  return TC_OK;
+}
+
+bool aligned(const void* p) { return ((uintptr_t)p % kAlign) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* tc_status_str(int st) {
+  switch (st) {
+    case TC_OK: return "ok";
+    case TC_ERR_INVALID_ARG: return "invalid argument";
+    case TC_ERR_SHAPE: return "inconsistent descriptor or weight count";
+    case TC_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case TC_ERR_UNSUPPORTED: return "unsupported precision or size";
+    case TC_ERR_HIP: return "HIP runtime or launch error";
+    default: return "unknown status";
+  }
+}
+
+const char* tc_version(void) { return "tcflow 0.1 (gfx950, fp32 MFMA)"; }
+
+size_t tc_weight_floats(const tc_net_desc* d) {
+  if (!desc_ok(d)) return 0;
+  const int ncv = (2 * d->radius + 1) * (2 * d->radius + 1);
+  size_t n = 0;
+  for (int l = 1; l <= d->levels; ++l) {
+    const int cin = l == 1 ? 3 : d->ch[l - 2];
+    n += conv_floats(d->ch[l - 1], cin) + conv_floats(d->ch[l - 1], d->ch[l - 1]);
+  }
+  for (int l = 1; l <= d->levels; ++l) {
+    n += conv_floats(d->dec[0], ncv + d->ch[l - 1] + 2) + conv_floats(d->dec[1], d->dec[0]) +
+         conv_floats(d->dec[2], d->dec[1]) + conv_floats(2, d->dec[1] + d->dec[2]);
+  }
+  return n;
+}
+
+int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_floats,
+                  int precision, tc_net** out) {
+  if (!desc || !host_weights || !out) return TC_ERR_INVALID_ARG;
+  if (!desc_ok(desc)) return TC_ERR_SHAPE;
+  if (precision != TC_FP32) return TC_ERR_UNSUPPORTED;
+  if (n_floats != tc_weight_floats(desc)) return TC_ERR_SHAPE;
+  tc_net* net = new (std::nothrow) tc_net();
+  if (!net) return TC_ERR_HIP;
+  net->d = *desc;
+  net->precision = precision;
+  net->ncv = (2 * desc->radius + 1) * (2 * desc->radius + 1);
+  net->zcb = (net->ncv + 2 + 7) / 8;
+  const int L = desc->levels;
+
+  // host packing
+  struct Packed {
+    std::vector<float> w, b;
+  };
+  std::vector<Packed> packed;
+  std::vector<ConvLayer*> slots;
+  const float* src = host_weights;
+  auto add_layer = [&](ConvLayer& cl, int cout, int cin, int kc, int cin_pad,
+                       const std::vector<int>& cmap) {
+    const float* W = src;
+    const float* b = src + (size_t)cout * cin * 9;
+    src += conv_floats(cout, cin);
+    Packed pk;
+    int np = 0;
+    pack_conv(W, b, cout, cin, kc, cin_pad, cmap, pk.w, pk.b, np);
+    cl.cin = cin;
+    cl.cout = cout;
+    cl.cin_pad = cin_pad;
+    cl.kc = kc;
+    cl.np = np;
+    packed.push_back(std::move(pk));
+    slots.push_back(&cl);
+  };
+  auto identity = [](int cin, int pad) {
+    std::vector<int> m(pad, -1);
+    for (int c = 0; c < cin; ++c) m[c] = c;
+    return m;
+  };
+  for (int l = 1; l <= L; ++l) {
+    const int C = desc->ch[l - 1];
+    const int cin = l == 1 ? 3 : desc->ch[l - 2];
+    const int kc = l == 1 ? 4 : 8;
+    const int pad = l == 1 ? 4 : cin;
+    add_layer(net->pyr[l - 1][0], C, cin, kc, pad, identity(cin, pad));
+    add_layer(net->pyr[l - 1][1], C, C, 8, C, identity(C, C));
+  }
+  const int d0 = desc->dec[0], d1 = desc->dec[1], d2 = desc->dec[2];
+  for (int l = 1; l <= L; ++l) {
+    const int C = desc->ch[l - 1];
+    // packed input order of c1: [F1 (C) | CV (ncv) | U (2) | zero pad];
+    // source order of the blob: [CV (ncv) | F1 (C) | U (2)].
+    const int pad = C + net->zcb * 8;
+    std::vector<int> m(pad, -1);
+    for (int g = 0; g < C; ++g) m[g] = net->ncv + g;
+    for (int k = 0; k < net->ncv; ++k) m[C + k] = k;
+    m[C + net->ncv] = net->ncv + C;
+    m[C + net->ncv + 1] = net->ncv + C + 1;
+    add_layer(net->dec[l - 1][0], d0, net->ncv + C + 2, 8, pad, m);
+    add_layer(net->dec[l - 1][1], d1, d0, 8, d0, identity(d0, d0));
+    add_layer(net->dec[l - 1][2], d2, d1, 8, d1, identity(d1, d1));
+    add_layer(net->dec[l - 1][3], 2, d1 + d2, 8, d1 + d2, identity(d1 + d2, d1 + d2));
+  }
+
+  // one device allocation for every layer
+  size_t total = 0;
+  std::vector<size_t> offs;
+  for (auto& pk : packed) {
+    offs.push_back(total);
+    total = align_up(total + pk.w.size() * sizeof(float), kAlign);
+    offs.push_back(total);
+    total = align_up(total + pk.b.size() * sizeof(float), kAlign);
+  }
+  if (hipMalloc(&net->dmem, total) != hipSuccess) {
+    delete net;
+    return TC_ERR_HIP;
+  }
+  std::vector<char> host(total, 0);
+  for (size_t i = 0; i < packed.size(); ++i) {
+    memcpy(host.data() + offs[2 * i], packed[i].w.data(), packed[i].w.size() * sizeof(float));
+    memcpy(host.data() + offs[2 * i + 1], packed[i].b.data(), packed[i].b.size() * sizeof(float));
+    slots[i]->w = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[2 * i]);
+    slots[i]->b = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[2 * i + 1]);
+  }
+  if (hipMemcpy(net->dmem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(net->dmem);
+    delete net;
+    return TC_ERR_HIP;
+  }
+  *out = net;
+  return TC_OK;
+}
+
+void tc_net_destroy(tc_net* net) {
+  if (!net) return;
+  if (net->dmem) (void)hipFree(net->dmem);
+  delete net;
+}
+
+size_t tc_pyramid_bytes(const tc_net* net, int n, int h, int w) {
+  if (!net || !shape_ok(n, h, w)) return 0;
+  return pyr_layout(net->d, n, h, w).total;
+}
+
+int tc_pyramid(const tc_net* net, const float* frames, int n, int h, int w, void* pyr,
+               size_t pyr_bytes, void* stream) {
+  if (!net || !frames || !pyr || !shape_ok(n, h, w)) return TC_ERR_INVALID_ARG;
+  if (!aligned(pyr) || pyr_bytes < tc_pyramid_bytes(net, n, h, w)) return TC_ERR_WORKSPACE;
+  return run_pyramid(net, frames, n, h, w, static_cast<char*>(pyr), (hipStream_t)stream);
+}
+
+size_t tc_decoder_workspace_bytes(const tc_net* net, int n, int h, int w) {
+  if (!net || !shape_ok(n, h, w)) return 0;
+  return dec_layout(net, 2 * n, h, w).total;
+}
+
+int tc_flow_from_pyramids(const tc_net* net, const void* pyr1, const void* pyr2, int n, int h,
+                          int w, float* flow12, float* flow21, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (!net || !pyr1 || !pyr2 || !flow12 || !ws || !shape_ok(n, h, w)) return TC_ERR_INVALID_ARG;
+  if (!aligned(ws) || !aligned(pyr1) || !aligned(pyr2)) return TC_ERR_WORKSPACE;
+  if (ws_bytes < dec_layout(net, flow21 ? 2 * n : n, h, w).total) return TC_ERR_WORKSPACE;
+  return run_decoder(net, static_cast<const char*>(pyr1), static_cast<const char*>(pyr2), n, h, w,
+                     flow12, flow21, static_cast<char*>(ws), (hipStream_t)stream);
+}
+
+size_t tc_flow_workspace_bytes(const tc_net* net, int n, int h, int w) {
+  if (!net || !shape_ok(n, h, w)) return 0;
+  return 2 * pyr_layout(net->d, n, h, w).total + dec_layout(net, 2 * n, h, w).total;
+}
+
+static int flow_common(const tc_net* net, const float* prev, const float* cur, int n, int h, int w,
+                       float* f12, float* f21, void* ws, size_t ws_bytes, void* stream) {
+  if (!net || !prev || !cur || !f12 || !ws || !shape_ok(n, h, w)) return TC_ERR_INVALID_ARG;
+  if (!aligned(ws) || ws_bytes < tc_flow_workspace_bytes(net, n, h, w)) return TC_ERR_WORKSPACE;
+  const size_t pb = pyr_layout(net->d, n, h, w).total;
+  char* base = static_cast<char*>(ws);
+  hipStream_t s = (hipStream_t)stream;
+  int st = run_pyramid(net, prev, n, h, w, base, s);
+  if (st) return st;
+  st = run_pyramid(net, cur, n, h, w, base + pb, s);
+  if (st) return st;
+  return run_decoder(net, base, base + pb, n, h, w, f12, f21, base + 2 * pb, s);
+}
+
+int tc_flow_estimate(const tc_net* net, const float* prev, const float* cur, int n, int h, int w,
+                     float* flow, void* ws, size_t ws_bytes, void* stream) {
+  return flow_common(net, prev, cur, n, h, w, flow, nullptr, ws, ws_bytes, stream);
+}
+
+int tc_flow_estimate_pair(const tc_net* net, const float* prev, const float* cur, int n, int h,
+                          int w, float* flow_fw, float* flow_bw, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (!flow_bw) return TC_ERR_INVALID_ARG;
+  return flow_common(net, prev, cur, n, h, w, flow_fw, flow_bw, ws, ws_bytes, stream);
+}
+
+int tc_consistency_step(const float* stylized, const float* prev_out, const float* flow_fw,
+                        const float* flow_bw, float alpha, int n, int h, int w, float* out,
+                        unsigned char* mask_or_null, void* stream) {
+  if (!stylized || !prev_out || !flow_fw || !flow_bw || !out) return TC_ERR_INVALID_ARG;
+  if (!shape_ok(n, h, w)) return TC_ERR_INVALID_ARG;
+  if (!(alpha >= 0.f && alpha <= 1.f)) return TC_ERR_INVALID_ARG;
+  if (out == prev_out || out == flow_fw || out == flow_bw) return TC_ERR_INVALID_ARG;
+  return launch_consistency(stylized, prev_out, flow_fw, flow_bw, alpha, n, h, w, out,
+                            mask_or_null, (hipStream_t)stream) == hipSuccess
+             ? TC_OK
+             : TC_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Fused consistency step: backward warp of O_{t-1}, forward-backward
+// visibility test, and the alpha-weighted blend with P_t, in one pass.
+// Paper Sec. 3.1 (Eq. 4: G_t = warp(O_{t-1}); Eq. 5: blend with the global
+// share clamped by the interactive strength) and Sec. 5 (non-occlusion mask
+// of Eq. 9 as a forward-backward consistency test).
+//
+// Bytes per pixel: P 12 + flow_bw 8 + O_{t-1} 12 + flow_fw 8 (gathered near
+// the pixel, so read about once) + out 12 = 52 (+1 with the mask).
+#include "tc_internal.h"
+
+namespace tc {
+namespace {
+
+// Bilinear taps of the point x + f along one axis of length n: integer part
+// taken from the flow alone so that the fraction is exact whatever x is.
+struct Taps {
+  int i0, i1;
+  float a;  // weight of i1
+};
+
+__device__ inline Taps axis_taps(int x, float f, int n) {
+  const float ff = floorf(f);
+  Taps t;
+  t.a = f - ff;
+  const float s = fminf(fmaxf((float)x + ff, -2.f), (float)n + 1.f);
+  const int i = (int)s;
+  t.i0 = min(max(i, 0), n - 1);
+  t.i1 = min(max(i + 1, 0), n - 1);
+  return t;
+}
+
+__global__ __launch_bounds__(256) void consistency_kernel(
+    const float* P, const float* __restrict__ Oprev, const float* __restrict__ ffw,
+    const float* __restrict__ fbw, float alpha, int n, int h, int w, float* out,
+    unsigned char* __restrict__ mask) {
+  const size_t plane = (size_t)h * w;
+  const size_t total = (size_t)n * plane;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t img = i / plane, pix = i - img * plane;
+    const int y = (int)(pix / w), x = (int)(pix - (size_t)y * w);
+    const float* fb = fbw + img * 2 * plane;
+    const float bx = fb[pix], by = fb[plane + pix];
+
+    // 0 <= x + bx <= w - 1, evaluated exactly in float
+    const bool inside = bx >= -(float)x && bx <= (float)(w - 1 - x) && by >= -(float)y &&
+                        by <= (float)(h - 1 - y);
+    const Taps tx = axis_taps(x, bx, w), ty = axis_taps(y, by, h);
+    const float w00 = (1.f - tx.a) * (1.f - ty.a), w01 = tx.a * (1.f - ty.a);
+    const float w10 = (1.f - tx.a) * ty.a, w11 = tx.a * ty.a;
+    const size_t o00 = (size_t)ty.i0 * w + tx.i0, o01 = (size_t)ty.i0 * w + tx.i1;
+    const size_t o10 = (size_t)ty.i1 * w + tx.i0, o11 = (size_t)ty.i1 * w + tx.i1;
+
+    const float* ff = ffw + img * 2 * plane;
+    const float fx = w00 * ff[o00] + w01 * ff[o01] + w10 * ff[o10] + w11 * ff[o11];
+    const float fy = w00 * ff[plane + o00] + w01 * ff[plane + o01] + w10 * ff[plane + o10] +
+                     w11 * ff[plane + o11];
+    const float sx = bx + fx, sy = by + fy;
+    const float lhs = sx * sx + sy * sy;
+    const float rhs = 0.01f * (bx * bx + by * by + fx * fx + fy * fy) + 0.5f;
+    const bool vis = inside && lhs <= rhs;
+
+    const float* Pi = P + img * 3 * plane;
+    const float* Oi = Oprev + img * 3 * plane;
+    float* oi = out + img * 3 * plane;
+    float res[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float* O = Oi + c * plane;
+      const float p = Pi[c * plane + pix];
+      if (vis) {
+        const float g = w00 * O[o00] + w01 * O[o01] + w10 * O[o10] + w11 * O[o11];
+        res[c] = (1.f - alpha) * p + alpha * g;
+      } else {
+        res[c] = p;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) oi[c * plane + pix] = res[c];
+    if (mask) mask[i] = vis ? 1 : 0;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_consistency(const float* P, const float* Oprev, const float* ffw,
+                              const float* fbw, float alpha, int n, int h, int w, float* out,
+                              unsigned char* mask, hipStream_t s) {
+  const size_t total = (size_t)n * h * w;
+  if (!total) return hipSuccess;
+  size_t g = (total + 255) / 256;
+  if (g > 1 << 20) g = 1 << 20;
+  consistency_kernel<<<(unsigned)g, 256, 0, s>>>(P, Oprev, ffw, fbw, alpha, n, h, w, out, mask);
+  return hipGetLastError();
+}
+
+}  // namespace tc

@@ -1,0 +1,249 @@
+// Bandwidth-bound steps of the flow network: frame staging, flow upsampling,
+// the fused feature warp + cost volume, and the final upsample-and-crop.
+#include "tc_internal.h"
+
+namespace tc {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- staging
+
+__global__ __launch_bounds__(256) void stage_kernel(const float* __restrict__ frames, int n, int h,
+                                                    int w, float* __restrict__ out, int hp, int wp) {
+  const size_t total = (size_t)n * hp * wp;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % wp);
+    const int y = (int)((i / wp) % hp);
+    const int img = (int)(i / ((size_t)wp * hp));
+    const int sy = y < h ? y : h - 1, sx = x < w ? x : w - 1;
+    const size_t plane = (size_t)h * w;
+    const float* f = frames + (size_t)img * 3 * plane + (size_t)sy * w + sx;
+    *reinterpret_cast<f4*>(out + i * 4) = f4{f[0], f[plane], f[2 * plane], 0.f};
+  }
+}
+
+// ---------------------------------------------------------------- up2
+
+// Source coordinate of output index i for 2x upsampling with half-pixel
+// centres: (i + 1/2) / 2 - 1/2 clamped to [0, n - 1]; exact in float.
+__device__ inline void up2_taps(int i, int n, int& i0, int& i1, float& f) {
+  float src = fmaxf((i + 0.5f) * 0.5f - 0.5f, 0.f);
+  i0 = min((int)src, n - 1);
+  f = src - (float)i0;
+  if (i0 >= n - 1) f = 0.f;
+  i1 = min(i0 + 1, n - 1);
+}
+
+__global__ __launch_bounds__(256) void up2x2_kernel(const float* __restrict__ flow, int n, int h,
+                                                    int w, float* __restrict__ U) {
+  const int H = 2 * h, W = 2 * w;
+  const size_t total = (size_t)n * H * W;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % W);
+    const int y = (int)((i / W) % H);
+    const int img = (int)(i / ((size_t)W * H));
+    int y0, y1, x0, x1;
+    float fy, fx;
+    up2_taps(y, h, y0, y1, fy);
+    up2_taps(x, w, x0, x1, fx);
+    const float2* f = reinterpret_cast<const float2*>(flow) + (size_t)img * h * w;
+    const float2 a = f[y0 * w + x0], b = f[y0 * w + x1], c = f[y1 * w + x0], d = f[y1 * w + x1];
+    float2 r;
+    r.x = 2.f * ((1.f - fy) * ((1.f - fx) * a.x + fx * b.x) + fy * ((1.f - fx) * c.x + fx * d.x));
+    r.y = 2.f * ((1.f - fy) * ((1.f - fx) * a.y + fx * b.y) + fy * ((1.f - fx) * c.y + fx * d.y));
+    reinterpret_cast<float2*>(U)[i] = r;
+  }
+}
+
+__global__ __launch_bounds__(256) void final_flow_kernel(const float* __restrict__ flow1, int n,
+                                                         int h1, int w1, float* __restrict__ out_a,
+                                                         float* __restrict__ out_b, int nsplit,
+                                                         int H, int W) {
+  const size_t total = (size_t)n * H * W;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % W);
+    const int y = (int)((i / W) % H);
+    const int img = (int)(i / ((size_t)W * H));
+    int y0, y1, x0, x1;
+    float fy, fx;
+    up2_taps(y, h1, y0, y1, fy);
+    up2_taps(x, w1, x0, x1, fx);
+    const float2* f = reinterpret_cast<const float2*>(flow1) + (size_t)img * h1 * w1;
+    const float2 a = f[y0 * w1 + x0], b = f[y0 * w1 + x1], c = f[y1 * w1 + x0], d = f[y1 * w1 + x1];
+    const float rx = 2.f * ((1.f - fy) * ((1.f - fx) * a.x + fx * b.x) + fy * ((1.f - fx) * c.x + fx * d.x));
+    const float ry = 2.f * ((1.f - fy) * ((1.f - fx) * a.y + fx * b.y) + fy * ((1.f - fx) * c.y + fx * d.y));
+    float* o = img < nsplit ? out_a + (size_t)img * 2 * H * W : out_b + (size_t)(img - nsplit) * 2 * H * W;
+    o[(size_t)y * W + x] = rx;
+    o[(size_t)H * W + (size_t)y * W + x] = ry;
+  }
+}
+
+// ---------------------------------------------------------------- warp + cost volume
+//
+// A workgroup owns a TY x TX tile of pixels (one per thread).  Per chunk of 8
+// channels it gathers the warped second-image features on the tile plus a
+// halo of R pixels into LDS (bilinear, zero outside), then every thread
+// accumulates its (2R+1)^2 correlations from LDS.  Layout of the LDS tile:
+// [2 float4 planes][halo positions][4] so that neighbouring lanes read
+// neighbouring 16-byte words.
+
+constexpr int CV_TY = 8, CV_TX = 32;
+
+__device__ inline const float* vbase(const View& v, int img, size_t img_floats) {
+  return img < v.nsplit ? v.a + (size_t)img * img_floats
+                        : v.b + (size_t)(img - v.nsplit) * img_floats;
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
+  constexpr int D = 2 * R + 1, NCV = D * D;
+  constexpr int HY = CV_TY + 2 * R, HX = CV_TX + 2 * R, NPOS = HY * HX;
+  __shared__ f4 s2[2][NPOS];
+
+  const int tid = threadIdx.x;
+  const int lx = tid % CV_TX, ly = tid / CV_TX;
+  const int tx0 = blockIdx.x * CV_TX, ty0 = blockIdx.y * CV_TY, img = blockIdx.z;
+  const int x = tx0 + lx, y = ty0 + ly;
+  const bool valid = x < a.w && y < a.h;
+  const int h = a.h, w = a.w;
+  const size_t plane = (size_t)h * w * 8;
+  const int ncb = a.C / 8;
+  const float* f1 = vbase(a.f1, img, plane * a.f1.cbt);
+  const float* f2 = vbase(a.f2, img, plane * a.f2.cbt);
+  const float2* U = a.U ? reinterpret_cast<const float2*>(a.U) + (size_t)img * h * w : nullptr;
+
+  float acc[NCV];
+#pragma unroll
+  for (int k = 0; k < NCV; ++k) acc[k] = 0.f;
+
+  for (int cb = 0; cb < ncb; ++cb) {
+    const float* f2c = f2 + (size_t)cb * plane;
+    for (int p = tid; p < NPOS; p += 256) {
+      const int py = p / HX, px = p - py * HX;
+      const int Y = ty0 - R + py, X = tx0 - R + px;
+      f4 lo = f4{0.f, 0.f, 0.f, 0.f}, hi = lo;
+      if (Y >= 0 && Y < h && X >= 0 && X < w) {
+        if (!U) {
+          const f4* s = reinterpret_cast<const f4*>(f2c + ((size_t)Y * w + X) * 8);
+          lo = s[0];
+          hi = s[1];
+        } else {
+          const float2 u = U[(size_t)Y * w + X];
+          const float fx = floorf(u.x), fy = floorf(u.y);
+          const float ax = u.x - fx, ay = u.y - fy;
+          const int x0 = X + (int)fx, y0 = Y + (int)fy;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int xi = x0 + (t & 1), yi = y0 + (t >> 1);
+            const float wt = ((t & 1) ? ax : 1.f - ax) * ((t >> 1) ? ay : 1.f - ay);
+            if (xi >= 0 && xi < w && yi >= 0 && yi < h) {
+              const f4* s = reinterpret_cast<const f4*>(f2c + ((size_t)yi * w + xi) * 8);
+              lo += wt * s[0];
+              hi += wt * s[1];
+            }
+          }
+        }
+      }
+      s2[0][p] = lo;
+      s2[1][p] = hi;
+    }
+    __syncthreads();
+    if (valid) {
+      const f4* s1 = reinterpret_cast<const f4*>(f1 + (size_t)cb * plane + ((size_t)y * w + x) * 8);
+      const f4 a0 = s1[0], a1 = s1[1];
+#pragma unroll
+      for (int dy = 0; dy < D; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < D; ++dx) {
+          const int p = (ly + dy) * HX + lx + dx;
+          const f4 b0 = s2[0][p], b1 = s2[1][p];
+          float s = acc[dy * D + dx];
+          s = fmaf(a0.x, b0.x, s);
+          s = fmaf(a0.y, b0.y, s);
+          s = fmaf(a0.z, b0.z, s);
+          s = fmaf(a0.w, b0.w, s);
+          s = fmaf(a1.x, b1.x, s);
+          s = fmaf(a1.y, b1.y, s);
+          s = fmaf(a1.z, b1.z, s);
+          s = fmaf(a1.w, b1.w, s);
+          acc[dy * D + dx] = s;
+        }
+    }
+    __syncthreads();
+  }
+  if (!valid) return;
+
+  // Z: blocks of 8 channels, [cv 0..NCV-1 | U_x | U_y | 0 ...]
+  const float invC = 1.f / (float)a.C;
+  float ux = 0.f, uy = 0.f;
+  if (U) {
+    const float2 u = U[(size_t)y * w + x];
+    ux = u.x;
+    uy = u.y;
+  }
+  float* z = a.Z + (size_t)img * a.zcb * plane + ((size_t)y * w + x) * 8;
+#pragma unroll
+  for (int b = 0; b < a.zcb; ++b) {
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int c = b * 8 + e;
+      float val = 0.f;
+      if (c < NCV) {
+        val = acc[c < NCV ? c : 0] * invC;
+        val = val >= 0.f ? val : a.slope * val;
+      } else if (c == NCV) {
+        val = ux;
+      } else if (c == NCV + 1) {
+        val = uy;
+      }
+      v[e] = val;
+    }
+    f4* d = reinterpret_cast<f4*>(z + (size_t)b * plane);
+    d[0] = f4{v[0], v[1], v[2], v[3]};
+    d[1] = f4{v[4], v[5], v[6], v[7]};
+  }
+}
+
+int grid_for(size_t total) {
+  size_t g = (total + 255) / 256;
+  return (int)(g < 65536 ? g : 65536);
+}
+
+}  // namespace
+
+hipError_t launch_stage(const float* frames, int n, int h, int w, float* out, int hp, int wp,
+                        hipStream_t s) {
+  const size_t total = (size_t)n * hp * wp;
+  if (!total) return hipSuccess;
+  stage_kernel<<<grid_for(total), 256, 0, s>>>(frames, n, h, w, out, hp, wp);
+  return hipGetLastError();
+}
+
+hipError_t launch_up2x2(const float* flow, int n, int h, int w, float* U, hipStream_t s) {
+  const size_t total = (size_t)n * 4 * h * w;
+  if (!total) return hipSuccess;
+  up2x2_kernel<<<grid_for(total), 256, 0, s>>>(flow, n, h, w, U);
+  return hipGetLastError();
+}
+
+hipError_t launch_final_flow(const float* flow1, int n, int h1, int w1, float* out_a, float* out_b,
+                             int nsplit, int H, int W, hipStream_t s) {
+  const size_t total = (size_t)n * H * W;
+  if (!total) return hipSuccess;
+  final_flow_kernel<<<grid_for(total), 256, 0, s>>>(flow1, n, h1, w1, out_a, out_b, nsplit, H, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_warp_cost_volume(const CvArgs& a, hipStream_t s) {
+  if (a.radius != 4 || a.C % 8 != 0) return hipErrorInvalidValue;
+  dim3 grid(cdiv(a.w, CV_TX), cdiv(a.h, CV_TY), a.n);
+  warp_cv_kernel<4><<<grid, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace tc

@@ -1,0 +1,92 @@
+// Internal declarations shared by the HIP translation units of libtcflow.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tc {
+
+constexpr int kBlock = 256;
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Activations are stored channel-blocked: element (img, c, y, x) of a buffer
+// with `cbt` blocks of B channels per image lives at
+//   base(img) + (((cb0 + c / B) * h + y) * w + x) * B + c % B
+// so a block of B channels of one pixel is contiguous and neighbouring pixels
+// are neighbouring in memory.  B = 8 everywhere except the staged RGB frame
+// (B = 4).  A view may split its batch over two buffers: images [0, nsplit)
+// come from `a`, the rest from `b` (index img - nsplit).
+struct View {
+  const float* a;
+  const float* b;
+  int nsplit;
+  int cbt;  // blocks per image in the underlying buffer
+  int cb0;  // first block of the view
+};
+
+// One 3x3 conv layer as the MFMA kernels consume it.  Weights are packed
+// [cin_pad / kc][9 taps][kc][np] (tap = 3 * p + q), zero for padded input or
+// output channels; np = cout rounded up to 16.  Bias has np entries.
+struct ConvLayer {
+  int cin, cout;   // real channel counts
+  int cin_pad;     // multiple of kc
+  int kc;          // input channels per K chunk (= block size of the input)
+  int np;          // cout rounded up to 16
+  float* w;        // device, packed
+  float* b;        // device, np floats
+};
+
+struct ConvArgs {
+  View in0, in1;  // K chunks [0, nb0) read in0, chunks [nb0, nchunks) read in1
+  int nb0;
+  int in_h, in_w;
+  float* out;     // blocked output (B = 8) ...
+  int out_cbt, out_cb0;
+  int compact;    // ... or compact NHWC with `cout` channels when nonzero
+  const float* add;  // compact NHWC (cout channels) added after the bias, or null
+  int out_h, out_w;
+  const float* w;
+  const float* b;
+  int nchunks, cout, np;
+  int lrelu;
+  float slope;
+  int n;  // images
+};
+
+hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, hipStream_t s);
+
+
+// NCHW float frames (n x 3 x h x w) -> blocked B = 4 (n x 1 x hp x wp x 4),
+// bottom/right edge replicated, channel 3 zero.
+hipError_t launch_stage(const float* frames, int n, int h, int w, float* out, int hp, int wp,
+                        hipStream_t s);
+
+// U = 2 * up2(flow), both compact NHWC with 2 channels: (n, h, w) -> (n, 2h, 2w).
+hipError_t launch_up2x2(const float* flow, int n, int h, int w, float* U, hipStream_t s);
+
+// Warp + cost volume: Z (blocked, B = 8, 11 blocks for radius 4) holds per
+// pixel [lrelu(CV_k / C), k < 81 | U_x | U_y | 0 ...].  F1 and F2 are blocked
+// pyramid levels with C / 8 blocks; U is compact NHWC (2 channels) or null
+// for zero flow.
+struct CvArgs {
+  View f1, f2;
+  const float* U;
+  float* Z;
+  int zcb;  // blocks per image of Z
+  int n, h, w, C, radius;
+  float slope;
+};
+hipError_t launch_warp_cost_volume(const CvArgs& a, hipStream_t s);
+
+// Output: flow NCHW (n x 2 x H x W) = crop(2 * up2(flow1)); flow1 NHWC
+// (n x h1 x w1 x 2).  Images [0, nsplit) go to out_a, the rest to out_b.
+hipError_t launch_final_flow(const float* flow1, int n, int h1, int w1, float* out_a,
+                             float* out_b, int nsplit, int H, int W, hipStream_t s);
+
+hipError_t launch_consistency(const float* P, const float* Oprev, const float* ffw,
+                              const float* fbw, float alpha, int n, int h, int w, float* out,
+                              unsigned char* mask, hipStream_t s);
+
+}  // namespace tc

@@ -1,0 +1,253 @@
+"""ctypes binding of libtcflow.so (argument marshalling only).
+
+Every function here forwards torch tensors' device pointers and the current
+HIP stream to the C ABI declared in include/tcflow.h; all computation happens
+in the library's HIP kernels.  If the library is missing or cannot be loaded
+the import of this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtcflow.so")
+
+TC_OK, TC_ERR_INVALID_ARG, TC_ERR_SHAPE, TC_ERR_WORKSPACE, TC_ERR_UNSUPPORTED, TC_ERR_HIP = range(6)
+TC_FP32, TC_BF16, TC_FP8_E4M3 = 0, 1, 2
+
+EXPORTS = (
+    "tc_status_str", "tc_version", "tc_weight_floats", "tc_net_create", "tc_net_destroy",
+    "tc_pyramid_bytes", "tc_pyramid", "tc_decoder_workspace_bytes", "tc_flow_from_pyramids",
+    "tc_flow_workspace_bytes", "tc_flow_estimate", "tc_flow_estimate_pair",
+    "tc_consistency_step",
+)
+
+
+class TcError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        super().__init__(f"{fn} failed: {status} ({_lib.tc_status_str(status).decode()})")
+
+
+class NetDesc(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("ch", ctypes.c_int * 8), ("dec", ctypes.c_int * 3),
+                ("radius", ctypes.c_int), ("leaky", ctypes.c_float)]
+
+    @classmethod
+    def from_dict(cls, d):
+        s = cls()
+        s.levels = d["levels"]
+        for i, c in enumerate(d["ch"]):
+            s.ch[i] = c
+        for i, c in enumerate(d["dec"]):
+            s.dec[i] = c
+        s.radius = d["radius"]
+        s.leaky = d["leaky"]
+        return s
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ci, cf, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_size_t
+    sig = {
+        "tc_status_str": (ctypes.c_char_p, [ci]),
+        "tc_version": (ctypes.c_char_p, []),
+        "tc_weight_floats": (sz, [ctypes.POINTER(NetDesc)]),
+        "tc_net_create": (ci, [ctypes.POINTER(NetDesc), vp, sz, ci, ctypes.POINTER(vp)]),
+        "tc_net_destroy": (None, [vp]),
+        "tc_pyramid_bytes": (sz, [vp, ci, ci, ci]),
+        "tc_pyramid": (ci, [vp, vp, ci, ci, ci, vp, sz, vp]),
+        "tc_decoder_workspace_bytes": (sz, [vp, ci, ci, ci]),
+        "tc_flow_from_pyramids": (ci, [vp, vp, vp, ci, ci, ci, vp, vp, vp, sz, vp]),
+        "tc_flow_workspace_bytes": (sz, [vp, ci, ci, ci]),
+        "tc_flow_estimate": (ci, [vp, vp, vp, ci, ci, ci, vp, vp, sz, vp]),
+        "tc_flow_estimate_pair": (ci, [vp, vp, vp, ci, ci, ci, vp, vp, vp, sz, vp]),
+        "tc_consistency_step": (ci, [vp, vp, vp, vp, cf, ci, ci, ci, vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(fn, st):
+    if st != TC_OK:
+        raise TcError(fn, st)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _frames(t, name, ch):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous() and t.dim() == 4 and t.shape[1] == ch):
+        raise ValueError(f"{name}: expected a contiguous cuda float32 tensor n x {ch} x h x w")
+    return t
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Net:
+    """A packed network on the current HIP device (tc_net_create)."""
+
+    def __init__(self, desc: dict, weights, precision: int = TC_FP32):
+        self.desc = dict(desc)
+        self._cdesc = NetDesc.from_dict(desc)
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+        h = ctypes.c_void_p()
+        _check("tc_net_create", _lib.tc_net_create(ctypes.byref(self._cdesc), w.ctypes.data,
+                                                   w.size, precision, ctypes.byref(h)))
+        self._h = h
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.tc_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # ---- sizes
+    def pyramid_bytes(self, n, h, w):
+        return _lib.tc_pyramid_bytes(self._h, n, h, w)
+
+    def decoder_workspace_bytes(self, n, h, w):
+        return _lib.tc_decoder_workspace_bytes(self._h, n, h, w)
+
+    def flow_workspace_bytes(self, n, h, w):
+        return _lib.tc_flow_workspace_bytes(self._h, n, h, w)
+
+    # ---- calls
+    def pyramid(self, frames, out=None, stream=None):
+        _frames(frames, "frames", 3)
+        n, _, h, w = frames.shape
+        nb = self.pyramid_bytes(n, h, w)
+        if out is None:
+            out = _workspace(nb, frames.device)
+        _check("tc_pyramid", _lib.tc_pyramid(self._h, _ptr(frames), n, h, w, _ptr(out),
+                                             out.numel() * out.element_size(), _stream(stream)))
+        return out
+
+    def flow_from_pyramids(self, pyr1, pyr2, n, h, w, both=True, ws=None, out12=None, out21=None,
+                           stream=None):
+        dev = pyr1.device
+        if ws is None:
+            ws = _workspace(self.decoder_workspace_bytes(n, h, w), dev)
+        f12 = out12 if out12 is not None else torch.empty(n, 2, h, w, device=dev)
+        f21 = (out21 if out21 is not None else torch.empty(n, 2, h, w, device=dev)) if both else None
+        _check("tc_flow_from_pyramids", _lib.tc_flow_from_pyramids(
+            self._h, _ptr(pyr1), _ptr(pyr2), n, h, w, _ptr(f12), _ptr(f21), _ptr(ws),
+            ws.numel() * ws.element_size(), _stream(stream)))
+        return (f12, f21) if both else f12
+
+    def flow_estimate(self, prev, cur, ws=None, out=None, stream=None):
+        _frames(prev, "prev", 3)
+        _frames(cur, "cur", 3)
+        if prev.shape != cur.shape:
+            raise ValueError("prev and cur differ in shape")
+        n, _, h, w = prev.shape
+        if ws is None:
+            ws = _workspace(self.flow_workspace_bytes(n, h, w), prev.device)
+        f = out if out is not None else torch.empty(n, 2, h, w, device=prev.device)
+        _check("tc_flow_estimate", _lib.tc_flow_estimate(
+            self._h, _ptr(prev), _ptr(cur), n, h, w, _ptr(f), _ptr(ws),
+            ws.numel() * ws.element_size(), _stream(stream)))
+        return f
+
+    def flow_estimate_pair(self, prev, cur, ws=None, out_fw=None, out_bw=None, stream=None):
+        _frames(prev, "prev", 3)
+        _frames(cur, "cur", 3)
+        if prev.shape != cur.shape:
+            raise ValueError("prev and cur differ in shape")
+        n, _, h, w = prev.shape
+        if ws is None:
+            ws = _workspace(self.flow_workspace_bytes(n, h, w), prev.device)
+        fw = out_fw if out_fw is not None else torch.empty(n, 2, h, w, device=prev.device)
+        bw = out_bw if out_bw is not None else torch.empty(n, 2, h, w, device=prev.device)
+        _check("tc_flow_estimate_pair", _lib.tc_flow_estimate_pair(
+            self._h, _ptr(prev), _ptr(cur), n, h, w, _ptr(fw), _ptr(bw), _ptr(ws),
+            ws.numel() * ws.element_size(), _stream(stream)))
+        return fw, bw
+
+
+def consistency_step(stylized, prev_out, flow_fw, flow_bw, alpha, out=None, mask=False,
+                     stream=None):
+    """out_t (and the uint8 visibility mask if ``mask``) from the C ABI."""
+    _frames(stylized, "stylized", 3)
+    _frames(prev_out, "prev_out", 3)
+    _frames(flow_fw, "flow_fw", 2)
+    _frames(flow_bw, "flow_bw", 2)
+    n, _, h, w = stylized.shape
+    for t in (prev_out, flow_fw, flow_bw):
+        if t.shape[0] != n or t.shape[2:] != stylized.shape[2:]:
+            raise ValueError("consistency_step: shapes differ")
+    o = out if out is not None else torch.empty_like(stylized)
+    m = torch.empty(n, h, w, dtype=torch.uint8, device=stylized.device) if mask else None
+    _check("tc_consistency_step", _lib.tc_consistency_step(
+        _ptr(stylized), _ptr(prev_out), _ptr(flow_fw), _ptr(flow_bw), float(alpha), n, h, w,
+        _ptr(o), _ptr(m), _stream(stream)))
+    return (o, m) if mask else o
+
+
+class StreamState:
+    """Streaming driver over the C ABI: O_1 = P_1; per new frame, the pyramid
+    of I_t (the previous one is kept), both flows from the two pyramids, and
+    the consistency step.  All buffers are allocated once."""
+
+    def __init__(self, net: Net, n: int, h: int, w: int, device="cuda"):
+        self.net, self.n, self.h, self.w = net, n, h, w
+        pb = net.pyramid_bytes(n, h, w)
+        self.pyr = [_workspace(pb, device), _workspace(pb, device)]
+        self.ws = _workspace(net.decoder_workspace_bytes(n, h, w), device)
+        self.fw = torch.empty(n, 2, h, w, device=device)
+        self.bw = torch.empty(n, 2, h, w, device=device)
+        self.out = [torch.empty(n, 3, h, w, device=device), torch.empty(n, 3, h, w, device=device)]
+        self.cur = 0
+        self.t = 0
+
+    def push(self, I, P, alpha, stream=None):
+        """Returns O_t (a view into an internal double buffer)."""
+        self.net.pyramid(I, out=self.pyr[self.cur], stream=stream)
+        if self.t == 0:
+            self.out[self.cur].copy_(P)
+        else:
+            prev = self.cur ^ 1
+            self.net.flow_from_pyramids(self.pyr[prev], self.pyr[self.cur], self.n, self.h, self.w,
+                                        both=True, ws=self.ws, out12=self.fw, out21=self.bw,
+                                        stream=stream)
+            consistency_step(P, self.out[prev], self.fw, self.bw, alpha, out=self.out[self.cur],
+                             stream=stream)
+        o = self.out[self.cur]
+        self.cur ^= 1
+        self.t += 1
+        return o

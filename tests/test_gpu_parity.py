@@ -1,0 +1,272 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Inputs come from paper_2301_00750_amd.synth (seeded) and are given to both
+sides unchanged (float32 on the GPU, the same values in float64 on the CPU).
+
+Tolerances
+  * flows: mean end-point error <= 0.05 px (the stated FP32 bar) and a
+    tighter bound derived from FP32 accumulation over K <= 1908 terms,
+    max |diff| <= 2e-3 px on the 128x96 workload;
+  * consistency output: 2e-6 absolute where the GPU and oracle masks agree
+    (values in [0, 1]; bilinear weights are formed exactly from the integer
+    part of the flow, leaving a few float32 roundings);
+  * the mask: identical wherever the oracle's margin exceeds 1e-5 (1 + terms);
+    inside that band either decision is valid and the output must equal the
+    oracle's output for the decision the GPU took.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import tcflow_oracle as O
+from paper_2301_00750_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tc():
+    from paper_2301_00750_amd import tcflow
+    assert torch.cuda.is_available()
+    return tcflow
+
+
+@pytest.fixture(scope="module")
+def tiny(tc):
+    d = synth.load_desc("tiny")
+    blob = synth.he_weights(d)
+    return d, blob, O.unpack_weights(blob, d), tc.Net(d, blob)
+
+
+def g(t):
+    return t.to(DEV).contiguous()
+
+
+def f64(t):
+    return t.detach().cpu().double().numpy()
+
+
+# ---------------------------------------------------------------- consistency
+
+
+def check_consistency(tc, P, Op, ffw, fbw, alpha, label):
+    say(f"[consistency] {label} shape={tuple(P.shape)} alpha={alpha}")
+    out, m = tc.consistency_step(g(P[None]), g(Op[None]), g(ffw[None]), g(fbw[None]), alpha,
+                                 mask=True)
+    torch.cuda.synchronize()
+    out = f64(out[0])
+    m = m[0].cpu().numpy().astype(bool)
+    ro, rm, margin, G = O.consistency(f64(P), f64(Op), f64(ffw), f64(fbw), alpha)
+    fb, fa = f64(fbw), O.warp_clamp(f64(ffw), f64(fbw))
+    scale = 1 + (fb ** 2).sum(0) + (fa ** 2).sum(0) + ((fb + fa) ** 2).sum(0)
+    amb = np.abs(margin) <= 1e-5 * scale
+    sure = ~amb
+    assert np.array_equal(m[sure], rm[sure]), f"{(m[sure] != rm[sure]).sum()} decided pixels differ"
+    # where undecided, the output matches the oracle's blend for the GPU's decision
+    alt = np.where(m[None], (1 - alpha) * f64(P) + alpha * G, f64(P))
+    err = np.abs(out - alt).max()
+    assert err <= 2e-6, f"max |out - oracle| = {err}"
+    assert np.abs(out[:, sure] - ro[:, sure]).max() <= 2e-6
+    say(f"   visible={m.mean():.3f} undecided={amb.mean():.2e} max_err={err:.2e}")
+    return out, m
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.25, 0.5, 0.75, 1.0])
+def test_consistency_layered_gt_flows(tc, alpha):
+    sc = synth.LayeredScene(331, 197, seed=3)
+    I0, I1 = sc.frame(0), sc.frame(1)
+    ffw, _ = sc.gt_flow(0, 1)
+    fbw, _ = sc.gt_flow(1, 0)
+    P1 = synth.stylize(I1, 1)
+    O0 = synth.stylize(I0, 0)
+    out, m = check_consistency(tc, P1, O0, ffw, fbw, alpha, "layered GT")
+    assert 0.5 < m.mean() < 1.0
+    if alpha == 0.0:
+        assert np.array_equal(out, f64(P1))
+
+
+def test_consistency_random_flows_ragged(tc):
+    gen = torch.Generator().manual_seed(7)
+    h, w = 77, 131
+    P = torch.rand(3, h, w, generator=gen)
+    Op = torch.rand(3, h, w, generator=gen)
+    ffw = 4 * torch.randn(2, h, w, generator=gen)
+    fbw = -ffw + 0.6 * torch.randn(2, h, w, generator=gen)
+    check_consistency(tc, P, Op, ffw, fbw, 0.6, "random flows")
+
+
+def test_consistency_integer_shift_exact(tc):
+    prev, cur, gfw, gbw = synth.tiny_pair()
+    out, m = tc.consistency_step(g(cur[None]), g(prev[None]), g(gfw[None]), g(gbw[None]), 1.0,
+                                 mask=True)
+    torch.cuda.synchronize()
+    h, w = prev.shape[1:]
+    assert int(m.sum()) == (w - 3) * (h - 2)
+    assert torch.equal(out[0].cpu(), cur)
+
+
+def test_consistency_alias_out_and_canaries(tc):
+    gen = torch.Generator().manual_seed(11)
+    h, w = 40, 56
+    P = torch.rand(2, 3, h, w, generator=gen)
+    Op = torch.rand(2, 3, h, w, generator=gen)
+    ffw = 2 * torch.randn(2, 2, h, w, generator=gen)
+    fbw = -ffw
+    ref = tc.consistency_step(g(P), g(Op), g(ffw), g(fbw), 0.5)
+    guard = torch.full((2 * 3 * h * w + 2048,), 7.0, device=DEV)
+    out = guard[1024:1024 + 2 * 3 * h * w].view(2, 3, h, w)
+    tc.consistency_step(g(P), g(Op), g(ffw), g(fbw), 0.5, out=out)
+    Pa = g(P)
+    tc.consistency_step(Pa, g(Op), g(ffw), g(fbw), 0.5, out=Pa)  # out aliases stylized
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref) and torch.equal(Pa, ref)
+    assert torch.all(guard[:1024] == 7.0) and torch.all(guard[-1024:] == 7.0)
+
+
+# ---------------------------------------------------------------- pyramid
+
+
+def unpack_pyramid(buf, d, n, h, w):
+    L = d["levels"]
+    m = 2 ** L
+    hp, wp = -(-h // m) * m, -(-w // m) * m
+    raw = buf.cpu()
+    pos, out = 0, []
+    for l in range(1, L + 1):
+        C, hl, wl = d["ch"][l - 1], hp >> l, wp >> l
+        nb = n * C * hl * wl * 4
+        a = raw[pos:pos + nb].view(torch.float32).reshape(n, C // 8, hl, wl, 8)
+        out.append(a.permute(0, 1, 4, 2, 3).reshape(n, C, hl, wl).double().numpy())
+        pos = (pos + nb + 255) // 256 * 256
+    return out
+
+
+@pytest.mark.parametrize("hw", [(96, 128), (75, 100)])
+def test_pyramid_vs_oracle(tc, tiny, hw):
+    d, blob, wts, net = tiny
+    h, w = hw
+    say(f"[pyramid] {h}x{w}")
+    gen = torch.Generator().manual_seed(5)
+    I = torch.rand(2, 3, h, w, generator=gen)
+    buf = net.pyramid(g(I))
+    torch.cuda.synchronize()
+    got = unpack_pyramid(buf, d, 2, h, w)
+    for i in range(2):
+        ref = O.pyramid(O.pad_frame(f64(I[i]), d["levels"]), wts, d)
+        for l, (a, b) in enumerate(zip(got, ref), start=1):
+            err = np.abs(a[i] - b).max() / max(1.0, np.abs(b).max())
+            assert err < 2e-5, f"level {l} image {i}: rel err {err}"
+
+
+# ---------------------------------------------------------------- flow
+
+
+def flow_err(a, b):
+    d = f64(a) - b
+    e = np.sqrt((d ** 2).sum(0))
+    return e.mean(), e.max()
+
+
+def sub_desc(d, levels):
+    s = dict(d)
+    s["levels"] = levels
+    s["ch"] = d["ch"][:levels]
+    return s
+
+
+@pytest.mark.parametrize("levels", [1, 2, 4])
+def test_flow_pair_tiny_vs_oracle(tc, levels):
+    d = sub_desc(synth.load_desc("tiny"), levels)
+    blob = synth.he_weights(d)
+    wts = O.unpack_weights(blob, d)
+    net = tc.Net(d, blob)
+    prev, cur, _, _ = synth.tiny_pair()
+    say(f"[flow] tiny levels={levels}")
+    fw, bw = net.flow_estimate_pair(g(prev[None]), g(cur[None]))
+    torch.cuda.synchronize()
+    rfw, rbw = O.flow_pair(f64(prev), f64(cur), wts, d)
+    for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
+        mean, mx = flow_err(a, b)
+        say(f"   {name}: EPE mean={mean:.3e} max={mx:.3e} |flow| rms={np.sqrt((b**2).sum(0).mean()):.2f}")
+        assert mean <= 0.05 and mx <= 2e-3
+
+
+def test_flow_single_batch_and_determinism(tc, tiny):
+    d, blob, wts, net = tiny
+    gen = torch.Generator().manual_seed(9)
+    h, w = 90, 150  # pads to 96 x 160
+    A = torch.rand(2, 3, h, w, generator=gen)
+    B = torch.rand(2, 3, h, w, generator=gen)
+    say(f"[flow] batch 2, {h}x{w}")
+    fw, bw = net.flow_estimate_pair(g(A), g(B))
+    fw2, bw2 = net.flow_estimate_pair(g(A), g(B))
+    f1 = net.flow_estimate(g(A), g(B))
+    s0 = net.flow_estimate_pair(g(A[:1]), g(B[:1]))
+    torch.cuda.synchronize()
+    assert torch.equal(fw, fw2) and torch.equal(bw, bw2)
+    assert torch.equal(f1, fw)
+    assert torch.equal(s0[0][0], fw[0]) and torch.equal(s0[1][0], bw[0])
+    rfw, rbw = O.flow_pair(f64(A[1]), f64(B[1]), wts, d)
+    assert flow_err(fw[1], rfw)[1] <= 2e-3 and flow_err(bw[1], rbw)[1] <= 2e-3
+
+
+def test_workspace_checks(tc, tiny):
+    d, blob, wts, net = tiny
+    A = g(torch.rand(1, 3, 32, 32))
+    need = net.flow_workspace_bytes(1, 32, 32)
+    small = torch.empty(need - 256, dtype=torch.uint8, device=DEV)
+    with pytest.raises(tc.TcError) as e:
+        net.flow_estimate(A, A, ws=small)
+    assert e.value.status == tc.TC_ERR_WORKSPACE
+    big = torch.empty(need + 512, dtype=torch.uint8, device=DEV)
+    with pytest.raises(tc.TcError) as e:
+        net.flow_estimate(A, A, ws=big[1:])  # misaligned
+    assert e.value.status == tc.TC_ERR_WORKSPACE
+
+
+def test_stream_state_sequence_vs_oracle(tc, tiny):
+    d, blob, wts, net = tiny
+    sc = synth.LayeredScene(128, 96, seed=1, max_shift=3.0)
+    I = [sc.frame(t) for t in range(4)]
+    P = [synth.stylize(x, t) for t, x in enumerate(I)]
+    st = tc.StreamState(net, 1, 96, 128)
+    outs = []
+    for t in range(4):
+        outs.append(f64(st.push(g(I[t][None]), g(P[t][None]), 0.75)[0]))
+    torch.cuda.synchronize()
+    # flows of the streaming path equal the stateless pair
+    fw, bw = net.flow_estimate_pair(g(I[2][None]), g(I[3][None]))
+    torch.cuda.synchronize()
+    assert torch.equal(fw, st.fw) and torch.equal(bw, st.bw)
+    ref = O.run_sequence([f64(x) for x in I], [f64(x) for x in P], wts, d, 0.75)
+    assert np.array_equal(outs[0], ref[0])
+    for t in range(1, 4):
+        err = np.abs(outs[t] - ref[t]).max()
+        say(f"   O_{t + 1}: max |GPU - oracle| = {err:.2e}")
+        assert err <= 1e-3
+
+
+def test_fullhd_pair_vs_oracle(tc):
+    d = synth.load_desc("fullhd")
+    blob = synth.he_weights(d)
+    wts = O.unpack_weights(blob, d)
+    net = tc.Net(d, blob)
+    sc = synth.LayeredScene(1920, 1080, seed=0)
+    I0, I1 = sc.frame(0), sc.frame(1)
+    say("[flow] 1920x1080 pair")
+    fw, bw = net.flow_estimate_pair(g(I0[None]), g(I1[None]))
+    torch.cuda.synchronize()
+    rfw, rbw = O.flow_pair(f64(I0), f64(I1), wts, d)
+    for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
+        mean, mx = flow_err(a, b)
+        say(f"   {name}: EPE mean={mean:.3e} max={mx:.3e}")
+        assert mean <= 0.05 and mx <= 0.05

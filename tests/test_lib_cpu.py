@@ -1,0 +1,105 @@
+"""The C-ABI library loads and exports every symbol include/tcflow.h declares;
+host-side argument checks return their documented status codes.  No GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2301_00750_amd import build_lib, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_path():
+    if not os.path.exists(build_lib.LIB):
+        build_lib.build()
+    return build_lib.LIB
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"TC_API\s+[\w\s\*]+?\b(tc_\w+)\s*\(", txt))
+    return names
+
+
+def test_header_declares_expected_calls():
+    names = declared_symbols()
+    for n in ("tc_flow_estimate", "tc_flow_estimate_pair", "tc_consistency_step",
+              "tc_net_create", "tc_net_destroy", "tc_flow_workspace_bytes", "tc_status_str"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib_path())
+    missing = [n for n in sorted(declared_symbols()) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_names_match_header():
+    _lib_path()
+    from paper_2301_00750_amd import tcflow
+    assert set(tcflow.EXPORTS) == declared_symbols()
+
+
+@pytest.fixture(scope="module")
+def tc():
+    _lib_path()
+    from paper_2301_00750_amd import tcflow
+    return tcflow
+
+
+@pytest.mark.parametrize("name", ["tiny", "fullhd"])
+def test_weight_floats_matches_generator(tc, name):
+    d = synth.load_desc(name)
+    cd = tc.NetDesc.from_dict(d)
+    assert tc.lib().tc_weight_floats(ctypes.byref(cd)) == synth.blob_floats(d)
+
+
+def test_status_strings(tc):
+    for st in range(6):
+        assert tc.lib().tc_status_str(st)
+    assert b"gfx950" in tc.lib().tc_version()
+
+
+def test_bad_descriptor_and_weight_count(tc):
+    d = synth.load_desc("tiny")
+    blob = synth.he_weights(d)
+    h = ctypes.c_void_p()
+    bad = dict(d, ch=[12, 32, 64, 96])  # not a multiple of 8
+    cd = tc.NetDesc.from_dict(bad)
+    assert tc.lib().tc_weight_floats(ctypes.byref(cd)) == 0
+    st = tc.lib().tc_net_create(ctypes.byref(cd), blob.ctypes.data, blob.size, 0, ctypes.byref(h))
+    assert st == tc.TC_ERR_SHAPE
+    cd = tc.NetDesc.from_dict(d)
+    st = tc.lib().tc_net_create(ctypes.byref(cd), blob.ctypes.data, blob.size - 1, 0, ctypes.byref(h))
+    assert st == tc.TC_ERR_SHAPE
+    st = tc.lib().tc_net_create(ctypes.byref(cd), blob.ctypes.data, blob.size, 7, ctypes.byref(h))
+    assert st == tc.TC_ERR_UNSUPPORTED
+    st = tc.lib().tc_net_create(ctypes.byref(cd), None, blob.size, 0, ctypes.byref(h))
+    assert st == tc.TC_ERR_INVALID_ARG
+    assert h.value is None
+
+
+def test_consistency_argument_checks(tc):
+    L = tc.lib()
+    p = ctypes.c_void_p(256)  # never dereferenced: every call below fails its checks first
+    assert L.tc_consistency_step(None, p, p, p, 0.5, 1, 4, 4, p, None, None) == tc.TC_ERR_INVALID_ARG
+    assert L.tc_consistency_step(p, p, p, p, 1.5, 1, 4, 4, ctypes.c_void_p(512), None, None) == tc.TC_ERR_INVALID_ARG
+    assert L.tc_consistency_step(p, p, p, p, float("nan"), 1, 4, 4, ctypes.c_void_p(512), None, None) == tc.TC_ERR_INVALID_ARG
+    assert L.tc_consistency_step(p, p, p, p, 0.5, 0, 4, 4, ctypes.c_void_p(512), None, None) == tc.TC_ERR_INVALID_ARG
+    assert L.tc_consistency_step(p, p, p, p, 0.5, 1, -3, 4, ctypes.c_void_p(512), None, None) == tc.TC_ERR_INVALID_ARG
+    # out aliasing prev_out is rejected
+    assert L.tc_consistency_step(p, p, ctypes.c_void_p(768), ctypes.c_void_p(1024), 0.5, 1, 4, 4, p, None, None) == tc.TC_ERR_INVALID_ARG
+
+
+def test_flow_argument_checks(tc):
+    L = tc.lib()
+    p = ctypes.c_void_p(256)
+    assert L.tc_flow_estimate(None, p, p, 1, 8, 8, p, p, 1 << 20, None) == tc.TC_ERR_INVALID_ARG
+    assert L.tc_pyramid_bytes(None, 1, 8, 8) == 0
+    assert L.tc_flow_workspace_bytes(None, 1, 8, 8) == 0
