@@ -1,0 +1,259 @@
+"""Throughput of the per-frame hot path at 1920x1080 on one MI355X.
+
+One step = one new frame of the streaming path: the feature pyramid of I_t
+(the pyramid of I_{t-1} is kept from the previous step), forward and backward
+flow decoded as one batch of two, and the fused consistency step producing
+O_t.  Inputs: a 60-frame 1920x1080 scene of three textured layers under
+seeded affine motion (played forward then backward), a seeded colour-map
+"stylizer", alpha swept over {0, .25, .5, .75, 1}; all frames resident in HBM
+before timing starts.  FP32 throughout.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2301_00750_amd import synth  # noqa: E402
+
+PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
+PEAK_HBM = 8000.0  # GB/s
+ALPHAS = (0.0, 0.25, 0.5, 0.75, 1.0)
+METRIC = "1080p frames/s (flow+consistency) at stated EPE vs FP64 oracle; p99 frame ms"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def frame_index(t, n):
+    """Forward then backward through n frames: 0..n-1, n-2..1, 0, ..."""
+    p = 2 * (n - 1)
+    k = t % p
+    return k if k < n else p - k
+
+
+def c1_flops(desc, h, w, level=1, images=2):
+    """Algorithmic FLOPs of one launch of the level-l decoder conv1 (fw + bw)."""
+    m = 2 ** desc["levels"]
+    hp, wp = -(-h // m) * m, -(-w // m) * m
+    px = images * (hp >> level) * (wp >> level)
+    ncv = (2 * desc["radius"] + 1) ** 2
+    din = ncv + desc["ch"][level - 1] + 2
+    return 2.0 * px * 9 * din * desc["dec"][0]
+
+
+def frame_lower_bound_ms(desc, h, w, peak_tflops, bpe=4):
+    """Sum over the unfused layer graph of max(FLOP / peak, bytes / HBM),
+    bytes = each layer's input read once + output written once."""
+    L, ch, dec = desc["levels"], desc["ch"], desc["dec"]
+    m = 2 ** L
+    hp, wp = -(-h // m) * m, -(-w // m) * m
+    ncv = (2 * desc["radius"] + 1) ** 2
+    t = 0.0
+
+    def layer(px_in, cin, px_out, cout, flops):
+        return max(flops / (peak_tflops * 1e12), (px_in * cin + px_out * cout) * bpe / (PEAK_HBM * 1e9))
+
+    # pyramid of one new frame
+    prev_px, prev_c = hp * wp, 3
+    for l in range(1, L + 1):
+        px = (hp >> l) * (wp >> l)
+        t += layer(prev_px, prev_c, px, ch[l - 1], 2.0 * px * 9 * prev_c * ch[l - 1])
+        t += layer(px, ch[l - 1], px, ch[l - 1], 2.0 * px * 9 * ch[l - 1] * ch[l - 1])
+        prev_px, prev_c = px, ch[l - 1]
+    for l in range(1, L + 1):
+        px = 2 * (hp >> l) * (wp >> l)  # fw + bw
+        C = ch[l - 1]
+        # warp + cost volume: read F1, F2 (+U), write 81 ch
+        t += layer(px, 2 * C + 2, px, ncv, 2.0 * px * ncv * C)
+        din = ncv + C + 2
+        t += layer(px, din, px, dec[0], 2.0 * px * 9 * din * dec[0])
+        t += layer(px, dec[0], px, dec[1], 2.0 * px * 9 * dec[0] * dec[1])
+        t += layer(px, dec[1], px, dec[2], 2.0 * px * 9 * dec[1] * dec[2])
+        t += layer(px, dec[1] + dec[2], px, 2, 2.0 * px * 9 * (dec[1] + dec[2]) * 2)
+    t += 52.0 * h * w / (PEAK_HBM * 1e9)  # consistency
+    return t * 1e3
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [i["num_threads"] for i in threadpool_info() if i.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return os.cpu_count()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--frames", type=int, default=60)
+    ap.add_argument("--cpu-frames", type=int, default=2,
+                    help="frames of the workload the FP64 oracle is timed on (0 = skip)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        log("bench.py measures one GPU only: the method is one stream on one device; "
+            "streams would shard across GPUs with no exchange, which is not built here.")
+        sys.exit(2)
+
+    from paper_2301_00750_amd import tcflow
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    desc = synth.load_desc("fullhd")
+    H, W = desc["height"], desc["width"]
+    blob = synth.he_weights(desc)
+    net = tcflow.Net(desc, blob)
+
+    log(f"generating {args.frames} frames {W}x{H} on the GPU")
+    scene = synth.LayeredScene(W, H, seed=0)
+    I = [scene.frame(t, device=dev)[None].contiguous() for t in range(args.frames)]
+    P = [synth.stylize(I[t][0], t)[None].contiguous() for t in range(args.frames)]
+    torch.cuda.synchronize()
+
+    st = tcflow.StreamState(net, 1, H, W, device=dev)
+
+    def step(t):
+        f = frame_index(t, args.frames)
+        st.push(I[f], P[f], ALPHAS[t % len(ALPHAS)])
+
+    log(f"warmup {args.warmup} steps")
+    for t in range(args.warmup + 1):  # step 0 only sets O_1 = P_1
+        step(t)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    probe_stage = tcflow.stage_id(1, tcflow.TC_OP_C1)
+    probe = tcflow.Probe(probe_stage, K)
+    log(f"timing {K} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        ev0[i].record()
+        step(args.warmup + 1 + i)
+        ev1[i].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_probe, probe_ms = probe.read()
+    probe.close()
+    wall = t1 - t0
+    fps = K / wall
+    lat = np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)])
+    log(f"{fps:.1f} frames/s, {1e3 * wall / K:.3f} ms/frame")
+
+    c1_avg_ms = probe_ms / max(1, n_probe)
+    c1_tflops = c1_flops(desc, H, W) / (c1_avg_ms * 1e-3) / 1e12
+    t_star = frame_lower_bound_ms(desc, H, W, PEAK_FP32_MFMA)
+
+    result = {
+        "metric": METRIC,
+        "value": round(fps, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * wall / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "1920x1080 streaming flow (fw+bw) + consistency, 60-frame 3-layer affine scene",
+            "resolution": [W, H],
+            "frames": args.frames,
+            "levels": desc["levels"],
+            "channels": desc["ch"],
+            "decoder": desc["dec"],
+            "alpha_sweep": list(ALPHAS),
+            "precision": "fp32",
+        },
+        "p50_frame_ms": round(float(np.percentile(lat, 50)), 4),
+        "p99_frame_ms": round(float(np.percentile(lat, 99)), 4),
+        "frame_roofline": {"t_star_ms": round(t_star, 4),
+                           "frac": round(t_star / (1e3 * wall / K), 4)},
+        "roofline": {
+            "kernel": "conv3x3_f32_mfma (level-1 decoder conv1, fw+bw batch)",
+            "bound": "mfma",
+            "achieved": round(c1_tflops, 2),
+            "peak": PEAK_FP32_MFMA,
+            "unit": "TFLOP/s",
+            "frac": round(c1_tflops / PEAK_FP32_MFMA, 4),
+            "traffic": None,
+            "avg_launch_ms": round(c1_avg_ms, 5),
+            "launches": n_probe,
+        },
+    }
+
+    if args.cpu_frames > 0:
+        result["cpu_baseline"], result["epe_vs_oracle"] = cpu_leg(net, desc, I, P, args.cpu_frames)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_leg(net, desc, I, P, nframes):
+    """Time the FP64 oracle on `nframes` frames of the same workload (flow
+    pair + consistency step with O_{t-1} = P_{t-1}) and compare the GPU's
+    flows, and its consistency step on the oracle's flows, with the oracle."""
+    from oracle import tcflow_oracle as O
+    from paper_2301_00750_amd import tcflow
+
+    wts = O.unpack_weights(synth.he_weights(desc), desc)
+    epes, maxes, oerr = [], [], []
+    cpu_s = 0.0
+    for t in range(1, nframes + 1):
+        fw, bw = net.flow_estimate_pair(I[t - 1], I[t])
+        torch.cuda.synchronize()
+        a64, b64 = I[t - 1][0].double().cpu().numpy(), I[t][0].double().cpu().numpy()
+        p64, q64 = P[t][0].double().cpu().numpy(), P[t - 1][0].double().cpu().numpy()
+        log(f"oracle frame {t}")
+        c0 = time.perf_counter()
+        rfw, rbw = O.flow_pair(a64, b64, wts, desc)
+        O.consistency(p64, q64, rfw, rbw, 0.5)
+        cpu_s += time.perf_counter() - c0
+        for g, r in ((fw, rfw), (bw, rbw)):
+            d = g[0].double().cpu().numpy() - r
+            e = np.sqrt((d ** 2).sum(0))
+            epes.append(float(e.mean()))
+            maxes.append(float(e.max()))
+        # the GPU consistency step on the oracle's flows (rounded to float32)
+        f32 = [torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32))[None].to(fw.device)
+               for x in (rfw, rbw)]
+        go = tcflow.consistency_step(P[t], P[t - 1], f32[0], f32[1], 0.5)
+        ro, _, margin, _ = O.consistency(p64, q64, rfw.astype(np.float32).astype(np.float64),
+                                         rbw.astype(np.float32).astype(np.float64), 0.5)
+        decided = np.abs(margin) > 1e-4
+        oerr.append(float(np.abs(go[0].double().cpu().numpy() - ro)[:, decided].max()))
+    base = {
+        "value": round(nframes / cpu_s, 5),
+        "unit": "frames/s",
+        "cores": blas_threads(),
+        "kind": "oracle",
+        "sample": f"{nframes} frames of the 1920x1080 workload: FP64 flow pair (both pyramids) "
+                  f"+ consistency step, {cpu_s:.1f} s",
+    }
+    epe = {"mean_px": max(epes), "max_px": max(maxes), "frames": nframes,
+           "consistency_max_abs": max(oerr), "tolerance_mean_px": 0.05}
+    return base, epe
+
+
+if __name__ == "__main__":
+    main()

@@ -136,6 +136,34 @@ TC_API int tc_consistency_step(const float* stylized, const float* prev_out, con
                                const float* flow_bw, float alpha, int n, int h, int w, float* out,
                                unsigned char* mask_or_null, void* stream);
 
+/* ---- measurement probe -------------------------------------------------- */
+
+/* Stage ids: TC_STAGE(level, op) for the per-level ops, plus three
+ * whole-frame stages. */
+#define TC_STAGE(level, op) ((level) * 16 + (op))
+enum {
+  TC_OP_PYR_A = 0,       /* pyramid stride-2 conv of level l          */
+  TC_OP_PYR_B = 1,       /* pyramid stride-1 conv of level l          */
+  TC_OP_UP2 = 2,         /* U_l = 2 up2(flow_{l+1})                   */
+  TC_OP_COST_VOLUME = 3, /* feature warp + cost volume of level l     */
+  TC_OP_C1 = 4,          /* decoder convs of level l                  */
+  TC_OP_C2 = 5,
+  TC_OP_C3 = 6,
+  TC_OP_HEAD = 7
+};
+#define TC_STAGE_INPUT 1        /* frame staging (pad + relayout)       */
+#define TC_STAGE_OUTPUT 2       /* final upsample + crop of the flow     */
+#define TC_STAGE_CONSISTENCY 3  /* fused consistency step               */
+
+/* Bracket every launch of `stage` with a pair of hipEvents on its stream,
+ * for up to `max_launches` launches (process-wide; a measurement aid, not
+ * thread safe; events are created here, outside any call path). */
+TC_API int tc_probe_enable(int stage, int max_launches);
+/* Waits for the recorded events; *launches = number recorded, *total_ms =
+ * summed device time between each pair.  Resets the count. */
+TC_API int tc_probe_read(int* launches, float* total_ms);
+TC_API void tc_probe_disable(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,6 +31,25 @@ constexpr size_t kAlign = 256;
     if ((x) != hipSuccess) return TC_ERR_HIP; \
   } while (0)
 
+// ---- measurement probe (see tc_probe_enable)
+struct Probe {
+  int stage = -1;
+  int count = 0;
+  std::vector<hipEvent_t> ev;  // 2 per launch
+};
+Probe g_probe;
+
+inline void probe_begin(int stage, hipStream_t s) {
+  if (stage == g_probe.stage && 2 * g_probe.count < (int)g_probe.ev.size())
+    (void)hipEventRecord(g_probe.ev[2 * g_probe.count], s);
+}
+inline void probe_end(int stage, hipStream_t s) {
+  if (stage == g_probe.stage && 2 * g_probe.count < (int)g_probe.ev.size()) {
+    (void)hipEventRecord(g_probe.ev[2 * g_probe.count + 1], s);
+    ++g_probe.count;
+  }
+}
+
 bool desc_ok(const tc_net_desc* d) {
   if (!d || d->levels < 1 || d->levels > 8) return false;
   for (int l = 0; l < d->levels; ++l)
@@ -147,7 +166,7 @@ View plain_view(const float* p, int cbt, int cb0 = 0) {
 
 int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, int in_h, int in_w,
                float* out, int out_cbt, int out_cb0, int compact, const float* add, int out_h,
-               int out_w, int relu, float slope, int n, int stride, hipStream_t s) {
+               int out_w, int relu, float slope, int n, int stride, int stage, hipStream_t s) {
   ConvArgs a;
   a.in0 = in0;
   a.in1 = in1;
@@ -169,7 +188,10 @@ int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, in
   a.lrelu = relu;
   a.slope = slope;
   a.n = n;
-  return launch_conv3x3(a, stride, L.kc, s) == hipSuccess ? TC_OK : TC_ERR_HIP;
+  probe_begin(stage, s);
+  const hipError_t e = launch_conv3x3(a, stride, L.kc, s);
+  probe_end(stage, s);
+  return e == hipSuccess ? TC_OK : TC_ERR_HIP;
 }
 
 int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, char* pyr,
@@ -179,7 +201,9 @@ int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, cha
   const PyrLayout p = pyr_layout(d, n, h, w);
   float* stage = reinterpret_cast<float*>(pyr + p.stage);
   float* tmp = reinterpret_cast<float*>(pyr + p.tmp);
+  probe_begin(TC_STAGE_INPUT, s);
   TC_TRY_HIP(launch_stage(frames, n, h, w, stage, g.hp, g.wp, s));
+  probe_end(TC_STAGE_INPUT, s);
   const float* in = stage;
   int in_cbt = 1, in_h = g.hp, in_w = g.wp;
   for (int l = 1; l <= d.levels; ++l) {
@@ -187,10 +211,11 @@ int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, cha
     float* feat = reinterpret_cast<float*>(pyr + p.off[l]);
     int st = conv_layer(net->pyr[l - 1][0], plain_view(in, in_cbt), net->pyr[l - 1][0].cin_pad / net->pyr[l - 1][0].kc,
                         plain_view(in, in_cbt), in_h, in_w, tmp, C / 8, 0, 0, nullptr, g.h[l], g.w[l],
-                        1, d.leaky, n, 2, s);
+                        1, d.leaky, n, 2, TC_STAGE(l, TC_OP_PYR_A), s);
     if (st) return st;
     st = conv_layer(net->pyr[l - 1][1], plain_view(tmp, C / 8), C / 8, plain_view(tmp, C / 8),
-                    g.h[l], g.w[l], feat, C / 8, 0, 0, nullptr, g.h[l], g.w[l], 1, d.leaky, n, 1, s);
+                    g.h[l], g.w[l], feat, C / 8, 0, 0, nullptr, g.h[l], g.w[l], 1, d.leaky, n, 1,
+                    TC_STAGE(l, TC_OP_PYR_B), s);
     if (st) return st;
     in = feat;
     in_cbt = C / 8;
@@ -224,7 +249,9 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
     f2.a = P2; f2.b = P1; f2.nsplit = n; f2.cbt = C / 8; f2.cb0 = 0;
     const float* Ul = nullptr;
     if (l < d.levels) {
+      probe_begin(TC_STAGE(l, TC_OP_UP2), s);
       TC_TRY_HIP(launch_up2x2(flows[cur], nb, g.h[l + 1], g.w[l + 1], U, s));
+      probe_end(TC_STAGE(l, TC_OP_UP2), s);
       Ul = U;
     }
     CvArgs cv;
@@ -239,24 +266,28 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
     cv.C = C;
     cv.radius = d.radius;
     cv.slope = d.leaky;
+    probe_begin(TC_STAGE(l, TC_OP_COST_VOLUME), s);
     TC_TRY_HIP(launch_warp_cost_volume(cv, s));
+    probe_end(TC_STAGE(l, TC_OP_COST_VOLUME), s);
     const ConvLayer* L = net->dec[l - 1];
     int st = conv_layer(L[0], f1, C / 8, plain_view(Z, net->zcb), hl, wl, H1, d0b, 0, 0, nullptr,
-                        hl, wl, 1, d.leaky, nb, 1, s);
+                        hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C1), s);
     if (st) return st;
     st = conv_layer(L[1], plain_view(H1, d0b), d0b, plain_view(H1, d0b), hl, wl, H23, d23b, 0, 0,
-                    nullptr, hl, wl, 1, d.leaky, nb, 1, s);
+                    nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C2), s);
     if (st) return st;
     st = conv_layer(L[2], plain_view(H23, d23b), d1b, plain_view(H23, d23b), hl, wl, H23, d23b,
-                    d1b, 0, nullptr, hl, wl, 1, d.leaky, nb, 1, s);
+                    d1b, 0, nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C3), s);
     if (st) return st;
     const int nxt = cur ^ 1;
     st = conv_layer(L[3], plain_view(H23, d23b), d23b, plain_view(H23, d23b), hl, wl, flows[nxt],
-                    0, 0, 1, Ul, hl, wl, 0, 0.f, nb, 1, s);
+                    0, 0, 1, Ul, hl, wl, 0, 0.f, nb, 1, TC_STAGE(l, TC_OP_HEAD), s);
     if (st) return st;
     cur = nxt;
   }
+  probe_begin(TC_STAGE_OUTPUT, s);
   TC_TRY_HIP(launch_final_flow(flows[cur], nb, g.h[1], g.w[1], flow12, flow21, n, h, w, s));
+  probe_end(TC_STAGE_OUTPUT, s);
   return TC_OK;
 }
 
@@ -462,10 +493,50 @@ int tc_consistency_step(const float* stylized, const float* prev_out, const floa
   if (!shape_ok(n, h, w)) return TC_ERR_INVALID_ARG;
   if (!(alpha >= 0.f && alpha <= 1.f)) return TC_ERR_INVALID_ARG;
   if (out == prev_out || out == flow_fw || out == flow_bw) return TC_ERR_INVALID_ARG;
-  return launch_consistency(stylized, prev_out, flow_fw, flow_bw, alpha, n, h, w, out,
-                            mask_or_null, (hipStream_t)stream) == hipSuccess
-             ? TC_OK
-             : TC_ERR_HIP;
+  probe_begin(TC_STAGE_CONSISTENCY, (hipStream_t)stream);
+  const hipError_t e = launch_consistency(stylized, prev_out, flow_fw, flow_bw, alpha, n, h, w,
+                                          out, mask_or_null, (hipStream_t)stream);
+  probe_end(TC_STAGE_CONSISTENCY, (hipStream_t)stream);
+  return e == hipSuccess ? TC_OK : TC_ERR_HIP;
+}
+
+int tc_probe_enable(int stage, int max_launches) {
+  if (max_launches <= 0 || max_launches > (1 << 20)) return TC_ERR_INVALID_ARG;
+  tc_probe_disable();
+  g_probe.ev.resize(2 * (size_t)max_launches);
+  for (auto& e : g_probe.ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      tc_probe_disable();
+      return TC_ERR_HIP;
+    }
+  g_probe.count = 0;
+  g_probe.stage = stage;
+  return TC_OK;
+}
+
+int tc_probe_read(int* launches, float* total_ms) {
+  if (!launches || !total_ms) return TC_ERR_INVALID_ARG;
+  float tot = 0.f;
+  for (int i = 0; i < g_probe.count; ++i) {
+    float ms = 0.f;
+    if (hipEventSynchronize(g_probe.ev[2 * i + 1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, g_probe.ev[2 * i], g_probe.ev[2 * i + 1]) != hipSuccess)
+      return TC_ERR_HIP;
+    tot += ms;
+  }
+  *launches = g_probe.count;
+  *total_ms = tot;
+  g_probe.count = 0;
+  return TC_OK;
+}
+
+void tc_probe_disable(void) {
+  for (auto& e : g_probe.ev)
+    if (e) (void)hipEventDestroy(e);
+  g_probe.ev.clear();
+  g_probe.count = 0;
+  g_probe.stage = -1;
 }
 
 }  // extern "C"

@@ -23,8 +23,15 @@ EXPORTS = (
     "tc_status_str", "tc_version", "tc_weight_floats", "tc_net_create", "tc_net_destroy",
     "tc_pyramid_bytes", "tc_pyramid", "tc_decoder_workspace_bytes", "tc_flow_from_pyramids",
     "tc_flow_workspace_bytes", "tc_flow_estimate", "tc_flow_estimate_pair",
-    "tc_consistency_step",
+    "tc_consistency_step", "tc_probe_enable", "tc_probe_read", "tc_probe_disable",
 )
+
+TC_OP_PYR_A, TC_OP_PYR_B, TC_OP_UP2, TC_OP_COST_VOLUME, TC_OP_C1, TC_OP_C2, TC_OP_C3, TC_OP_HEAD = range(8)
+TC_STAGE_INPUT, TC_STAGE_OUTPUT, TC_STAGE_CONSISTENCY = 1, 2, 3
+
+
+def stage_id(level, op):
+    return level * 16 + op
 
 
 class TcError(RuntimeError):
@@ -69,6 +76,9 @@ def _load():
         "tc_flow_estimate": (ci, [vp, vp, vp, ci, ci, ci, vp, vp, sz, vp]),
         "tc_flow_estimate_pair": (ci, [vp, vp, vp, ci, ci, ci, vp, vp, vp, sz, vp]),
         "tc_consistency_step": (ci, [vp, vp, vp, vp, cf, ci, ci, ci, vp, vp, vp]),
+        "tc_probe_enable": (ci, [ci, ci]),
+        "tc_probe_read": (ci, [ctypes.POINTER(ci), ctypes.POINTER(cf)]),
+        "tc_probe_disable": (None, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -217,6 +227,21 @@ def consistency_step(stylized, prev_out, flow_fw, flow_bw, alpha, out=None, mask
         _ptr(stylized), _ptr(prev_out), _ptr(flow_fw), _ptr(flow_bw), float(alpha), n, h, w,
         _ptr(o), _ptr(m), _stream(stream)))
     return (o, m) if mask else o
+
+
+class Probe:
+    """HIP-event timing of every launch of one stage (tc_probe_*)."""
+
+    def __init__(self, stage, max_launches):
+        _check("tc_probe_enable", _lib.tc_probe_enable(stage, max_launches))
+
+    def read(self):
+        n, ms = ctypes.c_int(), ctypes.c_float()
+        _check("tc_probe_read", _lib.tc_probe_read(ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+    def close(self):
+        _lib.tc_probe_disable()
 
 
 class StreamState:
