@@ -89,30 +89,42 @@ bool shape_ok(int n, int h, int w) {
 // frame (B = 4) and the scratch for each level's first conv.
 struct PyrLayout {
   size_t off[9];
-  size_t stage, tmp, total;
+  size_t stage, tmp, partial, total;
 };
 
-PyrLayout pyr_layout(const tc_net_desc& d, int n, int h, int w) {
+size_t layer_partial_bytes(const ConvLayer& L, int out_h, int out_w, int n, int stride) {
+  const ConvPlan p = plan_conv(out_h, out_w, n, L.cin_pad / L.kc, stride, L.np);
+  return conv_partial_bytes(p, out_h, out_w, n, L.np);
+}
+
+PyrLayout pyr_layout(const tc_net* net, int n, int h, int w) {
+  const tc_net_desc& d = net->d;
   PyrLayout p;
   LevelDims g = dims(d, h, w);
-  size_t pos = 0, tmp = 0;
+  size_t pos = 0, tmp = 0, part = 0;
   for (int l = 1; l <= d.levels; ++l) {
     const size_t bytes = (size_t)n * d.ch[l - 1] * g.h[l] * g.w[l] * sizeof(float);
     p.off[l] = pos;
     pos = align_up(pos + bytes, kAlign);
     if (bytes > tmp) tmp = bytes;
+    for (int k = 0; k < 2; ++k) {
+      const size_t pb = layer_partial_bytes(net->pyr[l - 1][k], g.h[l], g.w[l], n, k == 0 ? 2 : 1);
+      if (pb > part) part = pb;
+    }
   }
   p.stage = pos;
   pos = align_up(pos + (size_t)n * g.hp * g.wp * 4 * sizeof(float), kAlign);
   p.tmp = pos;
   pos = align_up(pos + tmp, kAlign);
+  p.partial = pos;
+  pos = align_up(pos + part, kAlign);
   p.total = pos;
   return p;
 }
 
 // ---- decoder scratch for a batch of nb images (n pairs -> nb = 2n)
 struct DecLayout {
-  size_t flow[2], U, Z, H1, H23, total;
+  size_t flow[2], U, Z, H1, H23, partial, total;
 };
 
 DecLayout dec_layout(const tc_net* net, int nb, int h, int w) {
@@ -131,6 +143,18 @@ DecLayout dec_layout(const tc_net* net, int nb, int h, int w) {
   L.Z = take(px * net->zcb * 8 * sizeof(float));
   L.H1 = take(px * net->d.dec[0] * sizeof(float));
   L.H23 = take(px * (net->d.dec[1] + net->d.dec[2]) * sizeof(float));
+  size_t part = 0;
+  for (int l = 1; l <= net->d.levels; ++l)
+    for (int k = 0; k < 3; ++k) {
+      const size_t pb = layer_partial_bytes(net->dec[l - 1][k], g.h[l], g.w[l], nb, 1);
+      if (pb > part) part = pb;
+    }
+  for (int l = 1; l <= net->d.levels; ++l) {
+    const size_t pb = cost_volume_partial_bytes(plan_cost_volume(g.h[l], g.w[l], net->d.ch[l - 1]),
+                                                nb, g.h[l], g.w[l]);
+    if (pb > part) part = pb;
+  }
+  L.partial = take(part);
   L.total = pos;
   return L;
 }
@@ -166,7 +190,8 @@ View plain_view(const float* p, int cbt, int cb0 = 0) {
 
 int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, int in_h, int in_w,
                float* out, int out_cbt, int out_cb0, int compact, const float* add, int out_h,
-               int out_w, int relu, float slope, int n, int stride, int stage, hipStream_t s) {
+               int out_w, int relu, float slope, int n, int stride, int stage, float* partial,
+               hipStream_t s) {
   ConvArgs a;
   a.in0 = in0;
   a.in1 = in1;
@@ -188,8 +213,19 @@ int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, in
   a.lrelu = relu;
   a.slope = slope;
   a.n = n;
+  a.partial = partial;
+  hipError_t e;
   probe_begin(stage, s);
-  const hipError_t e = launch_conv3x3(a, stride, L.kc, s);
+  if (L.cout == 2 && compact && stride == 1 && L.kc == 8) {  // estimator head
+    a.splits = 1;
+    a.cps = a.nchunks;
+    e = launch_head(a, s);
+  } else {
+    const ConvPlan p = plan_conv(out_h, out_w, n, a.nchunks, stride, L.np);
+    a.splits = p.splits;
+    a.cps = p.cps;
+    e = launch_conv3x3(a, stride, L.kc, p.mr, s);
+  }
   probe_end(stage, s);
   return e == hipSuccess ? TC_OK : TC_ERR_HIP;
 }
@@ -198,9 +234,10 @@ int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, cha
                 hipStream_t s) {
   const tc_net_desc& d = net->d;
   const LevelDims g = dims(d, h, w);
-  const PyrLayout p = pyr_layout(d, n, h, w);
+  const PyrLayout p = pyr_layout(net, n, h, w);
   float* stage = reinterpret_cast<float*>(pyr + p.stage);
   float* tmp = reinterpret_cast<float*>(pyr + p.tmp);
+  float* part = reinterpret_cast<float*>(pyr + p.partial);
   probe_begin(TC_STAGE_INPUT, s);
   TC_TRY_HIP(launch_stage(frames, n, h, w, stage, g.hp, g.wp, s));
   probe_end(TC_STAGE_INPUT, s);
@@ -211,11 +248,11 @@ int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, cha
     float* feat = reinterpret_cast<float*>(pyr + p.off[l]);
     int st = conv_layer(net->pyr[l - 1][0], plain_view(in, in_cbt), net->pyr[l - 1][0].cin_pad / net->pyr[l - 1][0].kc,
                         plain_view(in, in_cbt), in_h, in_w, tmp, C / 8, 0, 0, nullptr, g.h[l], g.w[l],
-                        1, d.leaky, n, 2, TC_STAGE(l, TC_OP_PYR_A), s);
+                        1, d.leaky, n, 2, TC_STAGE(l, TC_OP_PYR_A), part, s);
     if (st) return st;
     st = conv_layer(net->pyr[l - 1][1], plain_view(tmp, C / 8), C / 8, plain_view(tmp, C / 8),
                     g.h[l], g.w[l], feat, C / 8, 0, 0, nullptr, g.h[l], g.w[l], 1, d.leaky, n, 1,
-                    TC_STAGE(l, TC_OP_PYR_B), s);
+                    TC_STAGE(l, TC_OP_PYR_B), part, s);
     if (st) return st;
     in = feat;
     in_cbt = C / 8;
@@ -230,7 +267,7 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
                 float* flow12, float* flow21, char* ws, hipStream_t s) {
   const tc_net_desc& d = net->d;
   const LevelDims g = dims(d, h, w);
-  const PyrLayout p = pyr_layout(d, n, h, w);
+  const PyrLayout p = pyr_layout(net, n, h, w);
   const int nb = flow21 ? 2 * n : n;
   const DecLayout D = dec_layout(net, nb, h, w);
   float* flows[2] = {reinterpret_cast<float*>(ws + D.flow[0]), reinterpret_cast<float*>(ws + D.flow[1])};
@@ -238,6 +275,7 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
   float* Z = reinterpret_cast<float*>(ws + D.Z);
   float* H1 = reinterpret_cast<float*>(ws + D.H1);
   float* H23 = reinterpret_cast<float*>(ws + D.H23);
+  float* part = reinterpret_cast<float*>(ws + D.partial);
   const int d0b = d.dec[0] / 8, d1b = d.dec[1] / 8, d23b = (d.dec[1] + d.dec[2]) / 8;
   int cur = 0;
   for (int l = d.levels; l >= 1; --l) {
@@ -266,22 +304,26 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
     cv.C = C;
     cv.radius = d.radius;
     cv.slope = d.leaky;
+    const CvPlan cp = plan_cost_volume(hl, wl, C);
+    cv.splits = cp.splits;
+    cv.cps = cp.cps;
+    cv.partial = part;
     probe_begin(TC_STAGE(l, TC_OP_COST_VOLUME), s);
     TC_TRY_HIP(launch_warp_cost_volume(cv, s));
     probe_end(TC_STAGE(l, TC_OP_COST_VOLUME), s);
     const ConvLayer* L = net->dec[l - 1];
     int st = conv_layer(L[0], f1, C / 8, plain_view(Z, net->zcb), hl, wl, H1, d0b, 0, 0, nullptr,
-                        hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C1), s);
+                        hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C1), part, s);
     if (st) return st;
     st = conv_layer(L[1], plain_view(H1, d0b), d0b, plain_view(H1, d0b), hl, wl, H23, d23b, 0, 0,
-                    nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C2), s);
+                    nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C2), part, s);
     if (st) return st;
     st = conv_layer(L[2], plain_view(H23, d23b), d1b, plain_view(H23, d23b), hl, wl, H23, d23b,
-                    d1b, 0, nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C3), s);
+                    d1b, 0, nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C3), part, s);
     if (st) return st;
     const int nxt = cur ^ 1;
     st = conv_layer(L[3], plain_view(H23, d23b), d23b, plain_view(H23, d23b), hl, wl, flows[nxt],
-                    0, 0, 1, Ul, hl, wl, 0, 0.f, nb, 1, TC_STAGE(l, TC_OP_HEAD), s);
+                    0, 0, 1, Ul, hl, wl, 0, 0.f, nb, 1, TC_STAGE(l, TC_OP_HEAD), part, s);
     if (st) return st;
     cur = nxt;
   }
@@ -430,7 +472,7 @@ void tc_net_destroy(tc_net* net) {
 
 size_t tc_pyramid_bytes(const tc_net* net, int n, int h, int w) {
   if (!net || !shape_ok(n, h, w)) return 0;
-  return pyr_layout(net->d, n, h, w).total;
+  return pyr_layout(net, n, h, w).total;
 }
 
 int tc_pyramid(const tc_net* net, const float* frames, int n, int h, int w, void* pyr,
@@ -457,14 +499,14 @@ int tc_flow_from_pyramids(const tc_net* net, const void* pyr1, const void* pyr2,
 
 size_t tc_flow_workspace_bytes(const tc_net* net, int n, int h, int w) {
   if (!net || !shape_ok(n, h, w)) return 0;
-  return 2 * pyr_layout(net->d, n, h, w).total + dec_layout(net, 2 * n, h, w).total;
+  return 2 * pyr_layout(net, n, h, w).total + dec_layout(net, 2 * n, h, w).total;
 }
 
 static int flow_common(const tc_net* net, const float* prev, const float* cur, int n, int h, int w,
                        float* f12, float* f21, void* ws, size_t ws_bytes, void* stream) {
   if (!net || !prev || !cur || !f12 || !ws || !shape_ok(n, h, w)) return TC_ERR_INVALID_ARG;
   if (!aligned(ws) || ws_bytes < tc_flow_workspace_bytes(net, n, h, w)) return TC_ERR_WORKSPACE;
-  const size_t pb = pyr_layout(net->d, n, h, w).total;
+  const size_t pb = pyr_layout(net, n, h, w).total;
   char* base = static_cast<char*>(ws);
   hipStream_t s = (hipStream_t)stream;
   int st = run_pyramid(net, prev, n, h, w, base, s);

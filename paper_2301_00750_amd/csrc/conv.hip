@@ -1,13 +1,16 @@
 // 3x3 convolution (zero padding 1, stride 1 or 2) as an implicit GEMM on the
-// FP32 matrix cores of gfx950 (v_mfma_f32_16x16x4_f32).
+// FP32 matrix cores of gfx950 (v_mfma_f32_16x16x4_f32), plus the 2-channel
+// estimator head on vector ALUs.
 //
 // GEMM view: M = output pixels, N = output channels, K = 9 taps x input
-// channels.  A workgroup (4 waves) owns an 8 x 16 tile of output pixels and
-// every output channel; wave w computes output rows 2w and 2w+1 of the tile
-// (two 16-pixel M blocks) against NB 16-channel N blocks.  K runs over input
-// channel chunks of KC (= the block size of the input layout): per chunk the
-// input halo tile and the chunk's weights are staged in LDS, then 9 * KC / 4
-// MFMA steps consume them.
+// channels.  A workgroup (4 waves) owns a (4 * MR) x 16 tile of output pixels
+// and every output channel; wave w computes output rows MR*w .. MR*w + MR-1 of
+// the tile (MR 16-pixel M blocks) against NB 16-channel N blocks.  K runs over
+// input-channel chunks of KC (= the block size of the input layout): the next
+// chunk's input halo and weights are fetched into registers while the MFMAs
+// consume the current chunk from LDS.  Small layers split K over several
+// workgroups (grid z) and a reduction pass adds the partial sums in a fixed
+// order, so results do not depend on scheduling.
 //
 // MFMA 16x16x4 f32 operand layout (lane l of 64):
 //   A (16 x 4):  A[m = l % 16][k = l / 16]
@@ -20,7 +23,7 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int TH = 8, TW = 16;
+constexpr int TW = 16;
 
 // LDS row pitch that puts the four 16-lane groups of an MFMA operand read on
 // distinct bank ranges (pitch = 16 mod 32).
@@ -31,71 +34,118 @@ __device__ inline const float* view_base(const View& v, int img, size_t img_floa
                         : v.b + (size_t)(img - v.nsplit) * img_floats;
 }
 
-template <int S, int KC, int NB>
-__global__ __launch_bounds__(256) void conv3x3_f32_mfma(ConvArgs a) {
+__device__ inline float finish(const ConvArgs& a, float v, int n, size_t pix) {
+  v += a.b[n];
+  if (a.lrelu) v = v >= 0.f ? v : a.slope * v;
+  if (a.add) v += a.add[pix * a.cout + n];
+  return v;
+}
+
+__device__ inline void store_out(const ConvArgs& a, float v, int img, int oy, int ox, int n) {
+  const size_t pix = ((size_t)img * a.out_h + oy) * a.out_w + ox;
+  if (a.compact) {
+    a.out[pix * a.cout + n] = v;
+  } else {
+    const size_t plane = (size_t)a.out_h * a.out_w * 8;
+    a.out[(size_t)img * a.out_cbt * plane + (size_t)(a.out_cb0 + (n >> 3)) * plane +
+          ((size_t)oy * a.out_w + ox) * 8 + (n & 7)] = v;
+  }
+}
+
+template <int S, int KC, int NB, int MR>
+__global__ __launch_bounds__(256, 2) void conv3x3_f32_mfma(ConvArgs a) {
+  constexpr int TH = 4 * MR;
   constexpr int IH = (TH - 1) * S + 3, IW = (TW - 1) * S + 3;
   constexpr int NPOS = IH * IW;
   constexpr int APITCH = pitch16(NPOS);
   constexpr int NP = NB * 16;
   constexpr int BPITCH = pitch16(NP);
+  constexpr int NA = NPOS * (KC / 4);     // float4 of input per chunk
+  constexpr int NBW = 9 * KC * NP / 4;    // float4 of weights per chunk
+  constexpr int RA = (NA + 255) / 256, RB = (NBW + 255) / 256;
   __shared__ float sA[KC * APITCH];
   __shared__ float sB[9 * KC * BPITCH];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int tx0 = blockIdx.x * TW, ty0 = blockIdx.y * TH, img = blockIdx.z;
+  const int tx0 = blockIdx.x * TW, ty0 = blockIdx.y * TH;
+  const int img = blockIdx.z / a.splits, split = blockIdx.z - img * a.splits;
   const int iy0 = ty0 * S - 1, ix0 = tx0 * S - 1;
   const size_t in_plane = (size_t)a.in_h * a.in_w * KC;
+  const int c_begin = split * a.cps;
+  const int c_end = min(a.nchunks, c_begin + a.cps);
 
-  f4 acc[2][NB];
+  f4 acc[MR][NB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MR; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  const int lm = lane & 15, lk = lane >> 4;
-
-  for (int ch = 0; ch < a.nchunks; ++ch) {
-    // ---- stage the input halo tile of this channel chunk: sA[c][pos]
+  f4 ra[RA], rb[RB];
+  auto fetch = [&](int ch) {
     const View& v = ch < a.nb0 ? a.in0 : a.in1;
     const int cb = (ch < a.nb0 ? ch : ch - a.nb0) + v.cb0;
     const float* src = view_base(v, img, in_plane * v.cbt) + (size_t)cb * in_plane;
-    for (int i = tid; i < NPOS * (KC / 4); i += 256) {
-      const int pos = i / (KC / 4), c4 = i % (KC / 4);
-      const int py = pos / IW, px = pos - py * IW;
-      const int gy = iy0 + py, gx = ix0 + px;
-      f4 val = f4{0.f, 0.f, 0.f, 0.f};
-      if (gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w)
-        val = *reinterpret_cast<const f4*>(src + ((size_t)gy * a.in_w + gx) * KC + c4 * 4);
-      sA[(c4 * 4 + 0) * APITCH + pos] = val.x;
-      sA[(c4 * 4 + 1) * APITCH + pos] = val.y;
-      sA[(c4 * 4 + 2) * APITCH + pos] = val.z;
-      sA[(c4 * 4 + 3) * APITCH + pos] = val.w;
-    }
-    // ---- stage the chunk's weights: sB[tap * KC + c][n]
-    const f4* wsrc = reinterpret_cast<const f4*>(a.w + (size_t)ch * 9 * KC * NP);
-    for (int i = tid; i < 9 * KC * NP / 4; i += 256) {
-      const int row = i / (NP / 4), col = (i % (NP / 4)) * 4;
-      const f4 val = wsrc[i];
-      float* d = sB + row * BPITCH + col;
-      d[0] = val.x;
-      d[1] = val.y;
-      d[2] = val.z;
-      d[3] = val.w;
-    }
-    __syncthreads();
-
 #pragma unroll
+    for (int j = 0; j < RA; ++j) {
+      const int i = tid + j * 256;
+      f4 val = f4{0.f, 0.f, 0.f, 0.f};
+      if (i < NA) {
+        const int pos = i / (KC / 4), c4 = i % (KC / 4);
+        const int py = pos / IW, px = pos - py * IW;
+        const int gy = iy0 + py, gx = ix0 + px;
+        if (gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w)
+          val = *reinterpret_cast<const f4*>(src + ((size_t)gy * a.in_w + gx) * KC + c4 * 4);
+      }
+      ra[j] = val;
+    }
+    const f4* wsrc = reinterpret_cast<const f4*>(a.w + (size_t)ch * 9 * KC * NP);
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int i = tid + j * 256;
+      rb[j] = i < NBW ? wsrc[i] : f4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int j = 0; j < RA; ++j) {
+      const int i = tid + j * 256;
+      if (i < NA) {
+        const int pos = i / (KC / 4), c4 = i % (KC / 4);
+        sA[(c4 * 4 + 0) * APITCH + pos] = ra[j].x;
+        sA[(c4 * 4 + 1) * APITCH + pos] = ra[j].y;
+        sA[(c4 * 4 + 2) * APITCH + pos] = ra[j].z;
+        sA[(c4 * 4 + 3) * APITCH + pos] = ra[j].w;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int i = tid + j * 256;
+      if (i < NBW) {
+        const int row = i / (NP / 4), col = (i % (NP / 4)) * 4;
+        *reinterpret_cast<f4*>(sB + row * BPITCH + col) = rb[j];
+      }
+    }
+  };
+
+  const int lm = lane & 15, lk = lane >> 4;
+  if (c_begin < c_end) fetch(c_begin);
+  for (int ch = c_begin; ch < c_end; ++ch) {
+    stash();
+    __syncthreads();
+    if (ch + 1 < c_end) fetch(ch + 1);
+#pragma unroll 3
     for (int tap = 0; tap < 9; ++tap) {
       const int p = tap / 3, q = tap % 3;
 #pragma unroll
       for (int kk = 0; kk < KC / 4; ++kk) {
         float bf[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) bf[nb] = sB[(tap * KC + kk * 4 + lk) * BPITCH + nb * 16 + lm];
+        for (int nb = 0; nb < NB; ++nb)
+          bf[nb] = sB[(tap * KC + kk * 4 + lk) * BPITCH + nb * 16 + lm];
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-          const int r = wave * 2 + mb;
+        for (int mb = 0; mb < MR; ++mb) {
+          const int r = wave * MR + mb;
           const float af = sA[(kk * 4 + lk) * APITCH + (r * S + p) * IW + lm * S + q];
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb)
@@ -106,64 +156,217 @@ __global__ __launch_bounds__(256) void conv3x3_f32_mfma(ConvArgs a) {
     __syncthreads();
   }
 
-  // ---- epilogue: bias, LeakyReLU, optional flow accumulation, store
-  const size_t out_plane = (size_t)a.out_h * a.out_w * 8;
+  // ---- epilogue
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb) {
-    const int oy = ty0 + wave * 2 + mb;
+  for (int mb = 0; mb < MR; ++mb) {
+    const int oy = ty0 + wave * MR + mb;
     if (oy >= a.out_h) continue;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int n = nb * 16 + lm;
       if (n >= a.cout) continue;
-      const float bias = a.b[n];
 #pragma unroll
       for (int vv = 0; vv < 4; ++vv) {
         const int ox = tx0 + 4 * lk + vv;
         if (ox >= a.out_w) continue;
-        float val = acc[mb][nb][vv] + bias;
-        if (a.lrelu) val = val >= 0.f ? val : a.slope * val;
-        const size_t pix = ((size_t)img * a.out_h + oy) * a.out_w + ox;
-        if (a.compact) {
-          if (a.add) val += a.add[pix * a.cout + n];
-          a.out[pix * a.cout + n] = val;
+        if (a.splits > 1) {
+          a.partial[((((size_t)split * a.n + img) * a.out_h + oy) * a.out_w + ox) * NP + n] =
+              acc[mb][nb][vv];
         } else {
-          float* dst = a.out + (size_t)img * a.out_cbt * out_plane +
-                       (size_t)(a.out_cb0 + (n >> 3)) * out_plane +
-                       ((size_t)oy * a.out_w + ox) * 8 + (n & 7);
-          *dst = val;
+          const size_t pix = ((size_t)img * a.out_h + oy) * a.out_w + ox;
+          store_out(a, finish(a, acc[mb][nb][vv], n, pix), img, oy, ox, n);
         }
       }
     }
   }
 }
 
-template <int S, int KC>
+// Sum of the split-K partials in split order, then bias / LeakyReLU / add / store.
+__global__ __launch_bounds__(256) void conv_reduce_kernel(ConvArgs a) {
+  const size_t pixels = (size_t)a.n * a.out_h * a.out_w;
+  const size_t total = pixels * a.cout;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int n = (int)(i % a.cout);
+    const size_t pix = i / a.cout;
+    float s = 0.f;
+    for (int k = 0; k < a.splits; ++k) s += a.partial[((size_t)k * pixels + pix) * a.np + n];
+    const int ox = (int)(pix % a.out_w);
+    const int oy = (int)((pix / a.out_w) % a.out_h);
+    const int img = (int)(pix / ((size_t)a.out_w * a.out_h));
+    store_out(a, finish(a, s, n, pix), img, oy, ox, n);
+  }
+}
+
+// ---------------------------------------------------------------- head
+//
+// Two output channels on vector ALUs.  A workgroup owns 8 x 32 output
+// pixels; its 4 waves split the input-channel chunks (wave w takes chunks
+// w, w + 4, ...) and each lane accumulates 4 pixels (rows r, r + 2, r + 4,
+// r + 6 of its column), so every weight read from LDS feeds 8 FMAs.  The
+// four per-wave partial sums are added in wave order at the end, so the
+// result does not depend on scheduling or on the batch.
+constexpr int HD_TY = 8, HD_TX = 32, HD_MAXCH = 16;
+
+__global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
+  constexpr int HY = HD_TY + 2, HX = HD_TX + 2, NPOS = HY * HX;
+  __shared__ f4 s_in[4][2][NPOS];               // per wave: one 8-channel halo tile
+  __shared__ f4 s_w[HD_MAXCH * 9 * 4];          // [chunk][tap][channel pair] (w0 w1 of 2 channels)
+  float* s_red = reinterpret_cast<float*>(&s_in[0][0][0]);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tx0 = blockIdx.x * HD_TX, ty0 = blockIdx.y * HD_TY, img = blockIdx.z;
+  const size_t in_plane = (size_t)a.in_h * a.in_w * 8;
+
+  // weights: packed [chunk][tap][8][np] -> s_w[(chunk * 9 + tap) * 4 + pair] = (w0(c), w1(c), w0(c+1), w1(c+1))
+  for (int i = tid; i < a.nchunks * 9 * 4; i += 256) {
+    const int pair = i & 3, ct = i >> 2;
+    const float* src = a.w + (size_t)ct * 8 * a.np + 2 * pair * a.np;
+    s_w[i] = f4{src[0], src[1], src[a.np], src[a.np + 1]};
+  }
+
+  const int lx = lane & 31, ly0 = lane >> 5;  // lane's pixels: (ly0 + 2j, lx), j = 0..3
+  float o0[4] = {0.f, 0.f, 0.f, 0.f}, o1[4] = {0.f, 0.f, 0.f, 0.f};
+  const int rounds = (a.nchunks + 3) / 4;
+  for (int r = 0; r < rounds; ++r) {
+    const int ch = r * 4 + wave;
+    const bool active = ch < a.nchunks;
+    if (active) {
+      const View& v = ch < a.nb0 ? a.in0 : a.in1;
+      const int cb = (ch < a.nb0 ? ch : ch - a.nb0) + v.cb0;
+      const float* src = view_base(v, img, in_plane * v.cbt) + (size_t)cb * in_plane;
+      for (int p = lane; p < NPOS; p += 64) {
+        const int py = p / HX, px = p - py * HX;
+        const int gy = ty0 - 1 + py, gx = tx0 - 1 + px;
+        f4 lo = f4{0.f, 0.f, 0.f, 0.f}, hi = lo;
+        if (gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w) {
+          const f4* q = reinterpret_cast<const f4*>(src + ((size_t)gy * a.in_w + gx) * 8);
+          lo = q[0];
+          hi = q[1];
+        }
+        s_in[wave][0][p] = lo;
+        s_in[wave][1][p] = hi;
+      }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int ty = tap / 3, tx = tap % 3;
+        const f4* wt = s_w + (ch * 9 + tap) * 4;
+        const f4 w01 = wt[0], w23 = wt[1], w45 = wt[2], w67 = wt[3];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int p = (ly0 + 2 * j + ty) * HX + lx + tx;
+          const f4 lo = s_in[wave][0][p], hi = s_in[wave][1][p];
+          o0[j] = fmaf(lo.x, w01.x, o0[j]); o1[j] = fmaf(lo.x, w01.y, o1[j]);
+          o0[j] = fmaf(lo.y, w01.z, o0[j]); o1[j] = fmaf(lo.y, w01.w, o1[j]);
+          o0[j] = fmaf(lo.z, w23.x, o0[j]); o1[j] = fmaf(lo.z, w23.y, o1[j]);
+          o0[j] = fmaf(lo.w, w23.z, o0[j]); o1[j] = fmaf(lo.w, w23.w, o1[j]);
+          o0[j] = fmaf(hi.x, w45.x, o0[j]); o1[j] = fmaf(hi.x, w45.y, o1[j]);
+          o0[j] = fmaf(hi.y, w45.z, o0[j]); o1[j] = fmaf(hi.y, w45.w, o1[j]);
+          o0[j] = fmaf(hi.z, w67.x, o0[j]); o1[j] = fmaf(hi.z, w67.y, o1[j]);
+          o0[j] = fmaf(hi.w, w67.z, o0[j]); o1[j] = fmaf(hi.w, w67.w, o1[j]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // per-wave partials -> LDS [wave][pixel][2], then one pixel per thread
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int pix = (ly0 + 2 * j) * HD_TX + lx;
+    s_red[(wave * 256 + pix) * 2 + 0] = o0[j];
+    s_red[(wave * 256 + pix) * 2 + 1] = o1[j];
+  }
+  __syncthreads();
+  const int x = tx0 + (tid & 31), y = ty0 + (tid >> 5);
+  if (x >= a.out_w || y >= a.out_h) return;
+  float r0 = 0.f, r1 = 0.f;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    r0 += s_red[(w * 256 + tid) * 2 + 0];
+    r1 += s_red[(w * 256 + tid) * 2 + 1];
+  }
+  const size_t pix = ((size_t)img * a.out_h + y) * a.out_w + x;
+  store_out(a, finish(a, r0, 0, pix), img, y, x, 0);
+  store_out(a, finish(a, r1, 1, pix), img, y, x, 1);
+}
+
+template <int S, int KC, int MR>
 hipError_t dispatch_nb(const ConvArgs& a, hipStream_t s) {
-  dim3 grid(cdiv(a.out_w, TW), cdiv(a.out_h, TH), a.n);
+  dim3 grid(cdiv(a.out_w, TW), cdiv(a.out_h, 4 * MR), a.n * a.splits);
   switch (a.np / 16) {
-    case 1: conv3x3_f32_mfma<S, KC, 1><<<grid, 256, 0, s>>>(a); break;
-    case 2: conv3x3_f32_mfma<S, KC, 2><<<grid, 256, 0, s>>>(a); break;
-    case 3: conv3x3_f32_mfma<S, KC, 3><<<grid, 256, 0, s>>>(a); break;
-    case 4: conv3x3_f32_mfma<S, KC, 4><<<grid, 256, 0, s>>>(a); break;
-    case 5: conv3x3_f32_mfma<S, KC, 5><<<grid, 256, 0, s>>>(a); break;
-    case 6: conv3x3_f32_mfma<S, KC, 6><<<grid, 256, 0, s>>>(a); break;
-    case 7: conv3x3_f32_mfma<S, KC, 7><<<grid, 256, 0, s>>>(a); break;
-    case 8: conv3x3_f32_mfma<S, KC, 8><<<grid, 256, 0, s>>>(a); break;
+    case 1: conv3x3_f32_mfma<S, KC, 1, MR><<<grid, 256, 0, s>>>(a); break;
+    case 2: conv3x3_f32_mfma<S, KC, 2, MR><<<grid, 256, 0, s>>>(a); break;
+    case 3: conv3x3_f32_mfma<S, KC, 3, MR><<<grid, 256, 0, s>>>(a); break;
+    case 4: conv3x3_f32_mfma<S, KC, 4, MR><<<grid, 256, 0, s>>>(a); break;
+    case 5: conv3x3_f32_mfma<S, KC, 5, MR><<<grid, 256, 0, s>>>(a); break;
+    case 6: conv3x3_f32_mfma<S, KC, 6, MR><<<grid, 256, 0, s>>>(a); break;
+    case 7: conv3x3_f32_mfma<S, KC, 7, MR><<<grid, 256, 0, s>>>(a); break;
+    case 8: conv3x3_f32_mfma<S, KC, 8, MR><<<grid, 256, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+int grid_1d(size_t total) {
+  size_t g = (total + 255) / 256;
+  return (int)(g < 65536 ? g : 65536);
+}
+
 }  // namespace
 
-hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, hipStream_t s) {
+ConvPlan plan_conv(int out_h, int out_w, int n, int nchunks, int stride, int np) {
+  // Aim for >= ~512 workgroups per image (256 CUs, images usually come in
+  // pairs).  Large layers take the 16-row tile; small ones the 8-row tile and
+  // split K to make up the rest.  The plan depends on the per-image geometry
+  // only, never on the batch size n, so the summation order of every output
+  // (and hence its value, bit for bit) is the same alone and in a batch.
+  (void)n;
+  constexpr int kTarget = 512;
+  ConvPlan p{2, 1, nchunks};
+  if (stride == 1 && np <= 128 && (long)cdiv(out_h, 16) * cdiv(out_w, TW) >= 384) {
+    p.mr = 4;
+    return p;
+  }
+  const long t8 = (long)cdiv(out_h, 8) * cdiv(out_w, TW);
+  if (t8 < kTarget / 2) {
+    int splits = (int)((kTarget + t8 - 1) / t8);
+    if (splits > 16) splits = 16;
+    if (splits > nchunks) splits = nchunks;
+    const int cps = cdiv(nchunks, splits);
+    p.splits = cdiv(nchunks, cps);
+    p.cps = cps;
+  }
+  return p;
+}
+
+size_t conv_partial_bytes(const ConvPlan& p, int out_h, int out_w, int n, int np) {
+  return p.splits > 1 ? (size_t)p.splits * n * out_h * out_w * np * sizeof(float) : 0;
+}
+
+hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, int mr, hipStream_t s) {
   if (a.n <= 0 || a.out_h <= 0 || a.out_w <= 0) return hipSuccess;
-  if (stride == 1 && kc == 8) return dispatch_nb<1, 8>(a, s);
-  if (stride == 2 && kc == 8) return dispatch_nb<2, 8>(a, s);
-  if (stride == 2 && kc == 4) return dispatch_nb<2, 4>(a, s);
-  if (stride == 1 && kc == 4) return dispatch_nb<1, 4>(a, s);
-  return hipErrorInvalidValue;
+  if (a.splits < 1 || a.cps < 1 || (a.splits > 1 && !a.partial)) return hipErrorInvalidValue;
+  hipError_t e = hipErrorInvalidValue;
+  if (stride == 1 && kc == 8 && mr == 4) e = dispatch_nb<1, 8, 4>(a, s);
+  else if (stride == 1 && kc == 8 && mr == 2) e = dispatch_nb<1, 8, 2>(a, s);
+  else if (stride == 2 && kc == 8 && mr == 2) e = dispatch_nb<2, 8, 2>(a, s);
+  else if (stride == 2 && kc == 4 && mr == 2) e = dispatch_nb<2, 4, 2>(a, s);
+  else if (stride == 1 && kc == 4 && mr == 2) e = dispatch_nb<1, 4, 2>(a, s);
+  if (e != hipSuccess || a.splits == 1) return e;
+  const size_t total = (size_t)a.n * a.out_h * a.out_w * a.cout;
+  conv_reduce_kernel<<<grid_1d(total), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_head(const ConvArgs& a, hipStream_t s) {
+  if (a.n <= 0 || a.out_h <= 0 || a.out_w <= 0) return hipSuccess;
+  if (a.cout != 2 || a.np != 16 || a.nchunks > HD_MAXCH) return hipErrorInvalidValue;
+  dim3 grid(cdiv(a.out_w, HD_TX), cdiv(a.out_h, HD_TY), a.n);
+  head_kernel<<<grid, 256, 0, s>>>(a);
+  return hipGetLastError();
 }
 
 }  // namespace tc

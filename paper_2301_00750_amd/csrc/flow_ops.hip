@@ -106,12 +106,14 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
 
   const int tid = threadIdx.x;
   const int lx = tid % CV_TX, ly = tid / CV_TX;
-  const int tx0 = blockIdx.x * CV_TX, ty0 = blockIdx.y * CV_TY, img = blockIdx.z;
+  const int tx0 = blockIdx.x * CV_TX, ty0 = blockIdx.y * CV_TY;
+  const int img = blockIdx.z / a.splits, split = blockIdx.z - img * a.splits;
   const int x = tx0 + lx, y = ty0 + ly;
   const bool valid = x < a.w && y < a.h;
   const int h = a.h, w = a.w;
   const size_t plane = (size_t)h * w * 8;
-  const int ncb = a.C / 8;
+  const int cb_begin = split * a.cps;
+  const int cb_end = min(a.C / 8, cb_begin + a.cps);
   const float* f1 = vbase(a.f1, img, plane * a.f1.cbt);
   const float* f2 = vbase(a.f2, img, plane * a.f2.cbt);
   const float2* U = a.U ? reinterpret_cast<const float2*>(a.U) + (size_t)img * h * w : nullptr;
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
 #pragma unroll
   for (int k = 0; k < NCV; ++k) acc[k] = 0.f;
 
-  for (int cb = 0; cb < ncb; ++cb) {
+  for (int cb = cb_begin; cb < cb_end; ++cb) {
     const float* f2c = f2 + (size_t)cb * plane;
     for (int p = tid; p < NPOS; p += 256) {
       const int py = p / HX, px = p - py * HX;
@@ -176,6 +178,12 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
     __syncthreads();
   }
   if (!valid) return;
+  if (a.splits > 1) {
+    float* pp = a.partial + ((size_t)(split * a.n + img) * NCV) * h * w + (size_t)y * w + x;
+#pragma unroll
+    for (int k = 0; k < NCV; ++k) pp[(size_t)k * h * w] = acc[k];
+    return;
+  }
 
   // Z: blocks of 8 channels, [cv 0..NCV-1 | U_x | U_y | 0 ...]
   const float invC = 1.f / (float)a.C;
@@ -185,16 +193,17 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
     ux = u.x;
     uy = u.y;
   }
-  float* z = a.Z + (size_t)img * a.zcb * plane + ((size_t)y * w + x) * 8;
+  constexpr int ZCB = (NCV + 2 + 7) / 8;
+  float* z = a.Z + (size_t)img * ZCB * plane + ((size_t)y * w + x) * 8;
 #pragma unroll
-  for (int b = 0; b < a.zcb; ++b) {
+  for (int b = 0; b < ZCB; ++b) {
     float v[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int c = b * 8 + e;
       float val = 0.f;
       if (c < NCV) {
-        val = acc[c < NCV ? c : 0] * invC;
+        val = acc[c] * invC;
         val = val >= 0.f ? val : a.slope * val;
       } else if (c == NCV) {
         val = ux;
@@ -206,6 +215,33 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
     f4* d = reinterpret_cast<f4*>(z + (size_t)b * plane);
     d[0] = f4{v[0], v[1], v[2], v[3]};
     d[1] = f4{v[4], v[5], v[6], v[7]};
+  }
+}
+
+// Adds the channel splits of the cost volume in split order and writes Z:
+// one thread per (pixel, channel of Z), neighbouring threads on neighbouring
+// pixels so the partial reads are coalesced.
+template <int R>
+__global__ __launch_bounds__(256) void cv_reduce_kernel(CvArgs a) {
+  constexpr int D = 2 * R + 1, NCV = D * D, ZCB = (NCV + 2 + 7) / 8;
+  const size_t hw = (size_t)a.h * a.w;
+  const size_t total = (size_t)a.n * ZCB * 8 * hw;
+  const float invC = 1.f / (float)a.C;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t pix = i % hw;
+    const int c = (int)((i / hw) % (ZCB * 8));
+    const int img = (int)(i / (hw * ZCB * 8));
+    float val = 0.f;
+    if (c < NCV) {
+      for (int s = 0; s < a.splits; ++s)
+        val += a.partial[((size_t)(s * a.n + img) * NCV + c) * hw + pix];
+      val *= invC;
+      val = val >= 0.f ? val : a.slope * val;
+    } else if (c == NCV || c == NCV + 1) {
+      val = a.U ? a.U[((size_t)img * hw + pix) * 2 + (c - NCV)] : 0.f;
+    }
+    a.Z[((size_t)img * ZCB + (c >> 3)) * hw * 8 + pix * 8 + (c & 7)] = val;
   }
 }
 
@@ -239,10 +275,33 @@ hipError_t launch_final_flow(const float* flow1, int n, int h1, int w1, float* o
   return hipGetLastError();
 }
 
+CvPlan plan_cost_volume(int h, int w, int C) {
+  // Per-image geometry only (results do not depend on the batch): split the
+  // channel chunks when one image has fewer than 256 tiles.
+  CvPlan p{1, C / 8};
+  const long tiles = (long)cdiv(h, CV_TY) * cdiv(w, CV_TX);
+  const int nch = C / 8;
+  if (tiles < 256 && nch > 1) {
+    int splits = (int)((512 + tiles - 1) / tiles);
+    if (splits > nch) splits = nch;
+    p.cps = cdiv(nch, splits);
+    p.splits = cdiv(nch, p.cps);
+  }
+  return p;
+}
+
+size_t cost_volume_partial_bytes(const CvPlan& p, int n, int h, int w) {
+  return p.splits > 1 ? (size_t)p.splits * n * 81 * h * w * sizeof(float) : 0;
+}
+
 hipError_t launch_warp_cost_volume(const CvArgs& a, hipStream_t s) {
-  if (a.radius != 4 || a.C % 8 != 0) return hipErrorInvalidValue;
-  dim3 grid(cdiv(a.w, CV_TX), cdiv(a.h, CV_TY), a.n);
+  if (a.radius != 4 || a.C % 8 != 0 || a.zcb != (81 + 2 + 7) / 8) return hipErrorInvalidValue;
+  if (a.splits < 1 || a.cps < 1 || (a.splits > 1 && !a.partial)) return hipErrorInvalidValue;
+  dim3 grid(cdiv(a.w, CV_TX), cdiv(a.h, CV_TY), a.n * a.splits);
   warp_cv_kernel<4><<<grid, 256, 0, s>>>(a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.splits == 1) return e;
+  cv_reduce_kernel<4><<<grid_for((size_t)a.n * a.zcb * 8 * a.h * a.w), 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -53,9 +53,24 @@ struct ConvArgs {
   int lrelu;
   float slope;
   int n;  // images
+  // split-K: grid z = n * splits; split s handles chunks [s * cps, (s+1) * cps)
+  // and writes raw sums to partial[((s * n + img) * out_h + y) * out_w + x) * np + c];
+  // a reduction pass then applies bias, LeakyReLU, `add` and the store.
+  int splits, cps;
+  float* partial;
 };
 
-hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, hipStream_t s);
+// Launch plan of one conv: rows per wave (tile = 4 * mr rows x 16 columns)
+// and the number of K splits.  Shared by workspace sizing and launching.
+struct ConvPlan {
+  int mr, splits, cps;
+};
+ConvPlan plan_conv(int out_h, int out_w, int n, int nchunks, int stride, int np);
+size_t conv_partial_bytes(const ConvPlan& p, int out_h, int out_w, int n, int np);
+
+hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, int mr, hipStream_t s);
+// 3x3 conv with two output channels (the estimator head) on vector ALUs.
+hipError_t launch_head(const ConvArgs& a, hipStream_t s);
 
 
 // NCHW float frames (n x 3 x h x w) -> blocked B = 4 (n x 1 x hp x wp x 4),
@@ -77,7 +92,17 @@ struct CvArgs {
   int zcb;  // blocks per image of Z
   int n, h, w, C, radius;
   float slope;
+  // channel split: grid z = n * splits, split s sums chunks [s * cps, (s+1) * cps)
+  // into partial[((s * n + img) * 81 + k) * h * w + y * w + x]; a reduction
+  // pass adds the splits in order and writes Z.
+  int splits, cps;
+  float* partial;
 };
+struct CvPlan {
+  int splits, cps;
+};
+CvPlan plan_cost_volume(int h, int w, int C);
+size_t cost_volume_partial_bytes(const CvPlan& p, int n, int h, int w);
 hipError_t launch_warp_cost_volume(const CvArgs& a, hipStream_t s);
 
 // Output: flow NCHW (n x 2 x H x W) = crop(2 * up2(flow1)); flow1 NHWC

@@ -245,34 +245,63 @@ class Probe:
 
 
 class StreamState:
-    """Streaming driver over the C ABI: O_1 = P_1; per new frame, the pyramid
-    of I_t (the previous one is kept), both flows from the two pyramids, and
-    the consistency step.  All buffers are allocated once."""
+    """Streaming driver over the C ABI: O_1 = P_1; for each new frame, the
+    pyramid of I_t (the previous frame's pyramid is kept), both flows decoded
+    from the two pyramids in one batch, and the consistency step.
 
-    def __init__(self, net: Net, n: int, h: int, w: int, device="cuda"):
+    With ``pipelined`` the pyramid of each frame is built on a side stream,
+    so it overlaps the previous frame's decoder on the main (current) stream;
+    three pyramid slots and two events order the reuse.  Results are bitwise
+    the same either way.  All buffers are allocated once."""
+
+    def __init__(self, net: Net, n: int, h: int, w: int, device="cuda", pipelined=True):
         self.net, self.n, self.h, self.w = net, n, h, w
         pb = net.pyramid_bytes(n, h, w)
-        self.pyr = [_workspace(pb, device), _workspace(pb, device)]
+        self.pipelined = pipelined
+        nslots = 3 if pipelined else 2
+        self.pyr = [_workspace(pb, device) for _ in range(nslots)]
         self.ws = _workspace(net.decoder_workspace_bytes(n, h, w), device)
         self.fw = torch.empty(n, 2, h, w, device=device)
         self.bw = torch.empty(n, 2, h, w, device=device)
         self.out = [torch.empty(n, 3, h, w, device=device), torch.empty(n, 3, h, w, device=device)]
-        self.cur = 0
+        self.side = torch.cuda.Stream(device=device) if pipelined else None
+        self.pyr_done = [torch.cuda.Event() for _ in range(nslots)]
+        self.dec_done = [torch.cuda.Event() for _ in range(nslots)]
         self.t = 0
 
-    def push(self, I, P, alpha, stream=None):
-        """Returns O_t (a view into an internal double buffer)."""
-        self.net.pyramid(I, out=self.pyr[self.cur], stream=stream)
-        if self.t == 0:
-            self.out[self.cur].copy_(P)
+    def push(self, I, P, alpha, inputs_ready=False):
+        """Enqueue frame t; returns O_t (a view into an internal double buffer),
+        ordered on the current stream.
+
+        ``inputs_ready``: I is already complete on the device (no pending
+        work on the current stream writes it), so its pyramid may start at
+        once on the side stream; otherwise the side stream first waits for
+        the current stream, which keeps results correct but removes the
+        overlap."""
+        main = torch.cuda.current_stream()
+        ns = len(self.pyr)
+        slot, o = self.t % ns, self.t % 2
+        if self.pipelined:
+            # slot was last read by the decoder of frame t - 2 (t - ns + 1)
+            if self.t >= ns - 1:
+                self.side.wait_event(self.dec_done[(self.t - ns + 1) % ns])
+            if not inputs_ready:
+                self.side.wait_stream(main)
+            I.record_stream(self.side)
+            self.net.pyramid(I, out=self.pyr[slot], stream=self.side)
+            self.pyr_done[slot].record(self.side)
+            main.wait_event(self.pyr_done[slot])
         else:
-            prev = self.cur ^ 1
-            self.net.flow_from_pyramids(self.pyr[prev], self.pyr[self.cur], self.n, self.h, self.w,
+            self.net.pyramid(I, out=self.pyr[slot], stream=main)
+        if self.t == 0:
+            self.out[o].copy_(P)
+        else:
+            prev = (self.t - 1) % ns
+            self.net.flow_from_pyramids(self.pyr[prev], self.pyr[slot], self.n, self.h, self.w,
                                         both=True, ws=self.ws, out12=self.fw, out21=self.bw,
-                                        stream=stream)
-            consistency_step(P, self.out[prev], self.fw, self.bw, alpha, out=self.out[self.cur],
-                             stream=stream)
-        o = self.out[self.cur]
-        self.cur ^= 1
+                                        stream=main)
+            consistency_step(P, self.out[o ^ 1], self.fw, self.bw, alpha, out=self.out[o],
+                             stream=main)
+        self.dec_done[slot].record(main)
         self.t += 1
-        return o
+        return self.out[o]

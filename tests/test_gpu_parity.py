@@ -239,10 +239,14 @@ def test_stream_state_sequence_vs_oracle(tc, tiny):
     I = [sc.frame(t) for t in range(4)]
     P = [synth.stylize(x, t) for t, x in enumerate(I)]
     st = tc.StreamState(net, 1, 96, 128)
+    st2 = tc.StreamState(net, 1, 96, 128, pipelined=False)
     outs = []
     for t in range(4):
-        outs.append(f64(st.push(g(I[t][None]), g(P[t][None]), 0.75)[0]))
-    torch.cuda.synchronize()
+        o = st.push(g(I[t][None]), g(P[t][None]), 0.75)
+        o2 = st2.push(g(I[t][None]), g(P[t][None]), 0.75)
+        torch.cuda.synchronize()
+        assert torch.equal(o, o2)
+        outs.append(f64(o[0]))
     # flows of the streaming path equal the stateless pair
     fw, bw = net.flow_estimate_pair(g(I[2][None]), g(I[3][None]))
     torch.cuda.synchronize()
