@@ -3,8 +3,10 @@
 One step = one new frame of the streaming path: the feature pyramid of I_t
 (the pyramid of I_{t-1} is kept from the previous step), forward and backward
 flow decoded as one batch of two, and the fused consistency step producing
-O_t.  The pyramid of each frame runs on a side stream, overlapping the
-previous frame's decoder.  Inputs: a 60-frame 1920x1080 scene of three textured layers under
+O_t.  Throughput mode keeps several frames in flight: pyramids on a side
+stream and the decoders of consecutive frames on two streams (the flows of a
+frame do not depend on the previous frame's), consistency steps in order.
+Latency mode then pushes frames one at a time.  Inputs: a 60-frame 1920x1080 scene of three textured layers under
 seeded affine motion (played forward then backward), a seeded colour-map
 "stylizer", alpha swept over {0, .25, .5, .75, 1}; all frames resident in HBM
 before timing starts.  FP32 throughout.
@@ -107,6 +109,9 @@ def main():
     ap.add_argument("--frames", type=int, default=60)
     ap.add_argument("--cpu-frames", type=int, default=2,
                     help="frames of the workload the FP64 oracle is timed on (0 = skip)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="before timing, run 3 plain device copies of this many MiB (a known-size "
+                         "reference for hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -129,11 +134,19 @@ def main():
     P = [synth.stylize(I[t][0], t)[None].contiguous() for t in range(args.frames)]
     torch.cuda.synchronize()
 
+    if args.copy_mb > 0:
+        src = torch.empty(args.copy_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     st = tcflow.StreamState(net, 1, H, W, device=dev)
 
-    def step(t):
+    def step(t, events=None):
         f = frame_index(t, args.frames)
-        st.push(I[f], P[f], ALPHAS[t % len(ALPHAS)], inputs_ready=True)
+        st.push(I[f], P[f], ALPHAS[t % len(ALPHAS)], inputs_ready=True, events=events)
 
     log(f"warmup {args.warmup} steps")
     for t in range(args.warmup + 1):  # step 0 only sets O_1 = P_1
@@ -149,16 +162,27 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(K):
-        ev0[i].record()
-        step(args.warmup + 1 + i)
-        ev1[i].record()
+        step(args.warmup + 1 + i, events=(ev0[i], ev1[i]))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     n_probe, probe_ms = probe.read()
     probe.close()
     wall = t1 - t0
     fps = K / wall
-    lat = np.array([a.elapsed_time(b) for a, b in zip(ev0, ev1)])
+    gaps = np.diff(np.array([ev1[0].elapsed_time(e) for e in ev1]))
+
+    # latency mode: one frame at a time, as a live stream sees it (the frame's
+    # first kernel to its output, nothing else in flight)
+    NL = min(60, K)
+    lev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(NL)]
+    probe = tcflow.Probe(probe_stage, NL)
+    for i in range(NL):
+        step(args.warmup + 1 + K + i, events=lev[i])
+        torch.cuda.synchronize()
+    n_alone, alone_ms = probe.read()
+    probe.close()
+    lat = np.array([a.elapsed_time(b) for a, b in lev])
     log(f"{fps:.1f} frames/s, {1e3 * wall / K:.3f} ms/frame")
 
     c1_avg_ms = probe_ms / max(1, n_probe)
@@ -190,6 +214,10 @@ def main():
         },
         "p50_frame_ms": round(float(np.percentile(lat, 50)), 4),
         "p99_frame_ms": round(float(np.percentile(lat, 99)), 4),
+        "frame_ms_definition": f"latency of one frame pushed alone ({NL} frames): its first kernel "
+                               "(pyramid) to O_t ready",
+        "p50_output_interval_ms": round(float(np.percentile(gaps, 50)), 4),
+        "p99_output_interval_ms": round(float(np.percentile(gaps, 99)), 4),
         "frame_roofline": {"t_star_ms": round(t_star, 4),
                            "frac": round(t_star / (1e3 * wall / K), 4)},
         "roofline": {
@@ -202,6 +230,10 @@ def main():
             "traffic": None,
             "avg_launch_ms": round(c1_avg_ms, 5),
             "launches": n_probe,
+            "note": "launches timed inside the throughput run, where two frames' decoders "
+                    "share the GPU; alone_* = the same kernel in the latency pass",
+            "alone_avg_launch_ms": round(alone_ms / max(1, n_alone), 5),
+            "alone_achieved": round(c1_flops(desc, H, W) / (alone_ms / max(1, n_alone) * 1e-3) / 1e12, 2),
         },
     }
 

@@ -129,29 +129,38 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_mfma(ConvArgs a) {
   };
 
   const int lm = lane & 15, lk = lane >> 4;
+  // fragment addresses: K step ks = tap * (KC / 4) + kk
+  const float* sAw = sA + lk * APITCH + wave * MR * S * IW + lm * S;
+  const float* sBw = sB + lk * BPITCH + lm;
+  constexpr int KS = 9 * (KC / 4);
+  auto load_frags = [&](int ks, float (&fa)[MR], float (&fb)[NB]) {
+    const int tap = ks / (KC / 4), kk = ks % (KC / 4);
+    const int p = tap / 3, q = tap % 3;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) fb[nb] = sBw[(tap * KC + kk * 4) * BPITCH + nb * 16];
+#pragma unroll
+    for (int mb = 0; mb < MR; ++mb) fa[mb] = sAw[kk * 4 * APITCH + (mb * S + p) * IW + q];
+  };
+
   if (c_begin < c_end) fetch(c_begin);
   for (int ch = c_begin; ch < c_end; ++ch) {
     stash();
     __syncthreads();
     if (ch + 1 < c_end) fetch(ch + 1);
-#pragma unroll 3
-    for (int tap = 0; tap < 9; ++tap) {
-      const int p = tap / 3, q = tap % 3;
+    // software pipeline: the fragments of step ks + 1 are read from LDS
+    // while the MFMAs of step ks run
+    float fa[2][MR], fb[2][NB];
+    load_frags(0, fa[0], fb[0]);
 #pragma unroll
-      for (int kk = 0; kk < KC / 4; ++kk) {
-        float bf[NB];
+    for (int ks = 0; ks < KS; ++ks) {
+      const int cur = ks & 1;
+      if (ks + 1 < KS) load_frags(ks + 1, fa[cur ^ 1], fb[cur ^ 1]);
+#pragma unroll
+      for (int mb = 0; mb < MR; ++mb)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
-          bf[nb] = sB[(tap * KC + kk * 4 + lk) * BPITCH + nb * 16 + lm];
-#pragma unroll
-        for (int mb = 0; mb < MR; ++mb) {
-          const int r = wave * MR + mb;
-          const float af = sA[(kk * 4 + lk) * APITCH + (r * S + p) * IW + lm * S + q];
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf[nb], acc[mb][nb], 0, 0, 0);
-        }
-      }
+          acc[mb][nb] =
+              __builtin_amdgcn_mfma_f32_16x16x4f32(fa[cur][mb], fb[cur][nb], acc[mb][nb], 0, 0, 0);
     }
     __syncthreads();
   }

@@ -249,29 +249,39 @@ class StreamState:
     pyramid of I_t (the previous frame's pyramid is kept), both flows decoded
     from the two pyramids in one batch, and the consistency step.
 
-    With ``pipelined`` the pyramid of each frame is built on a side stream,
-    so it overlaps the previous frame's decoder on the main (current) stream;
-    three pyramid slots and two events order the reuse.  Results are bitwise
-    the same either way.  All buffers are allocated once."""
+    ``pipelined`` spreads the work over HIP streams: pyramids on one side
+    stream, the flow decoders of consecutive frames alternately on two more
+    (the flows of frame t do not depend on those of frame t - 1; only the
+    consistency step is sequential), and the consistency steps in order on
+    the caller's current stream.  Events order every buffer reuse.  Results
+    are bitwise the same with and without pipelining.  All buffers are
+    allocated once."""
 
     def __init__(self, net: Net, n: int, h: int, w: int, device="cuda", pipelined=True):
         self.net, self.n, self.h, self.w = net, n, h, w
-        pb = net.pyramid_bytes(n, h, w)
         self.pipelined = pipelined
-        nslots = 3 if pipelined else 2
-        self.pyr = [_workspace(pb, device) for _ in range(nslots)]
-        self.ws = _workspace(net.decoder_workspace_bytes(n, h, w), device)
-        self.fw = torch.empty(n, 2, h, w, device=device)
-        self.bw = torch.empty(n, 2, h, w, device=device)
+        pb = net.pyramid_bytes(n, h, w)
+        self.ns = 4 if pipelined else 2          # pyramid slots
+        self.nd = 2 if pipelined else 1          # decoder lanes
+        self.pyr = [_workspace(pb, device) for _ in range(self.ns)]
+        wb = net.decoder_workspace_bytes(n, h, w)
+        self.ws = [_workspace(wb, device) for _ in range(self.nd)]
+        self.fw = [torch.empty(n, 2, h, w, device=device) for _ in range(self.nd)]
+        self.bw = [torch.empty(n, 2, h, w, device=device) for _ in range(self.nd)]
         self.out = [torch.empty(n, 3, h, w, device=device), torch.empty(n, 3, h, w, device=device)]
-        self.side = torch.cuda.Stream(device=device) if pipelined else None
-        self.pyr_done = [torch.cuda.Event() for _ in range(nslots)]
-        self.dec_done = [torch.cuda.Event() for _ in range(nslots)]
+        if pipelined:
+            self.s_pyr = torch.cuda.Stream(device=device)
+            self.s_dec = [torch.cuda.Stream(device=device) for _ in range(self.nd)]
+        self.ev_pyr = [torch.cuda.Event() for _ in range(self.ns)]
+        self.ev_dec = [torch.cuda.Event() for _ in range(self.ns)]   # by frame % ns
+        self.ev_con = [torch.cuda.Event() for _ in range(self.nd)]   # by frame % nd
         self.t = 0
 
-    def push(self, I, P, alpha, inputs_ready=False):
+    def push(self, I, P, alpha, inputs_ready=False, events=None):
         """Enqueue frame t; returns O_t (a view into an internal double buffer),
-        ordered on the current stream.
+        ordered on the current stream.  ``events`` = (start, end) CUDA events
+        recorded right before this frame's first kernel and after its last
+        one (frame latency).
 
         ``inputs_ready``: I is already complete on the device (no pending
         work on the current stream writes it), so its pyramid may start at
@@ -279,29 +289,70 @@ class StreamState:
         the current stream, which keeps results correct but removes the
         overlap."""
         main = torch.cuda.current_stream()
-        ns = len(self.pyr)
-        slot, o = self.t % ns, self.t % 2
-        if self.pipelined:
-            # slot was last read by the decoder of frame t - 2 (t - ns + 1)
-            if self.t >= ns - 1:
-                self.side.wait_event(self.dec_done[(self.t - ns + 1) % ns])
-            if not inputs_ready:
-                self.side.wait_stream(main)
-            I.record_stream(self.side)
-            self.net.pyramid(I, out=self.pyr[slot], stream=self.side)
-            self.pyr_done[slot].record(self.side)
-            main.wait_event(self.pyr_done[slot])
-        else:
+        t, ns, nd = self.t, self.ns, self.nd
+        slot, lane, o = t % ns, t % nd, t % 2
+        if not self.pipelined:
+            if events:
+                events[0].record(main)
             self.net.pyramid(I, out=self.pyr[slot], stream=main)
-        if self.t == 0:
+            if t > 0:
+                self._decode_and_blend(t, P, alpha, main, main)
+            else:
+                self.out[o].copy_(P)
+            if events:
+                events[1].record(main)
+            self.t += 1
+            return self.out[o]
+
+        sp = self.s_pyr
+        # slot t % ns last held frame t - ns, read by the decoders of frames
+        # t - ns and t - ns + 1
+        for k in (t - ns, t - ns + 1):
+            if k >= 1:
+                sp.wait_event(self.ev_dec[k % ns])
+        if not inputs_ready:
+            sp.wait_stream(main)
+        I.record_stream(sp)
+        if events:
+            events[0].record(sp)
+        self.net.pyramid(I, out=self.pyr[slot], stream=sp)
+        self.ev_pyr[slot].record(sp)
+        if t == 0:
+            main.wait_event(self.ev_pyr[slot])
             self.out[o].copy_(P)
         else:
-            prev = (self.t - 1) % ns
-            self.net.flow_from_pyramids(self.pyr[prev], self.pyr[slot], self.n, self.h, self.w,
-                                        both=True, ws=self.ws, out12=self.fw, out21=self.bw,
-                                        stream=main)
-            consistency_step(P, self.out[o ^ 1], self.fw, self.bw, alpha, out=self.out[o],
-                             stream=main)
-        self.dec_done[slot].record(main)
+            sd = self.s_dec[lane]
+            sd.wait_event(self.ev_pyr[slot])
+            if t - nd >= 1:  # flow buffers of this lane were read by consistency(t - nd)
+                sd.wait_event(self.ev_con[lane])
+            self._decode(t, sd)
+            self.ev_dec[slot].record(sd)
+            main.wait_event(self.ev_dec[slot])
+            self._blend(t, P, alpha, main)
+            self.ev_con[lane].record(main)
+        if events:
+            events[1].record(main)
         self.t += 1
         return self.out[o]
+
+    def _decode(self, t, stream):
+        lane = t % self.nd
+        prev, cur = (t - 1) % self.ns, t % self.ns
+        self.net.flow_from_pyramids(self.pyr[prev], self.pyr[cur], self.n, self.h, self.w,
+                                    both=True, ws=self.ws[lane], out12=self.fw[lane],
+                                    out21=self.bw[lane], stream=stream)
+
+    def _blend(self, t, P, alpha, stream):
+        lane, o = t % self.nd, t % 2
+        consistency_step(P, self.out[o ^ 1], self.fw[lane], self.bw[lane], alpha,
+                         out=self.out[o], stream=stream)
+
+    def _decode_and_blend(self, t, P, alpha, sdec, smain):
+        self._decode(t, sdec)
+        self._blend(t, P, alpha, smain)
+
+    @property
+    def flows(self):
+        """(flow_fw, flow_bw) of the last pushed frame (after synchronising)."""
+        lane = (self.t - 1) % self.nd
+        return self.fw[lane], self.bw[lane]

@@ -247,10 +247,24 @@ def test_stream_state_sequence_vs_oracle(tc, tiny):
         torch.cuda.synchronize()
         assert torch.equal(o, o2)
         outs.append(f64(o[0]))
+    # many frames through the pipelined driver with inputs resident up front:
+    # every output equals the unpipelined driver's
+    Ig = [g(x[None]) for x in I] * 3
+    Pg = [g(x[None]) for x in P] * 3
+    torch.cuda.synchronize()
+    st3 = tc.StreamState(net, 1, 96, 128)
+    st4 = tc.StreamState(net, 1, 96, 128, pipelined=False)
+    res3, res4 = [], []
+    for t in range(len(Ig)):
+        res3.append(st3.push(Ig[t], Pg[t], 0.5, inputs_ready=True).clone())
+        res4.append(st4.push(Ig[t], Pg[t], 0.5).clone())
+    torch.cuda.synchronize()
+    for a3, a4 in zip(res3, res4):
+        assert torch.equal(a3, a4)
     # flows of the streaming path equal the stateless pair
     fw, bw = net.flow_estimate_pair(g(I[2][None]), g(I[3][None]))
     torch.cuda.synchronize()
-    assert torch.equal(fw, st.fw) and torch.equal(bw, st.bw)
+    assert torch.equal(fw, st.flows[0]) and torch.equal(bw, st.flows[1])
     ref = O.run_sequence([f64(x) for x in I], [f64(x) for x in P], wts, d, 0.75)
     assert np.array_equal(outs[0], ref[0])
     for t in range(1, 4):
