@@ -9,7 +9,9 @@ frame do not depend on the previous frame's), consistency steps in order.
 Latency mode then pushes frames one at a time.  Inputs: a 60-frame 1920x1080 scene of three textured layers under
 seeded affine motion (played forward then backward), a seeded colour-map
 "stylizer", alpha swept over {0, .25, .5, .75, 1}; all frames resident in HBM
-before timing starts.  FP32 throughout.
+before timing starts.  The headline is the FP32 path; the BF16 form (BF16
+activations and weights on MFMA with FP32 accumulation; flows, upsampling and
+warp coordinates in FP32) is measured after it with its EPE and speedup.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -31,6 +33,7 @@ sys.path.insert(0, ROOT)
 from paper_2301_00750_amd import synth  # noqa: E402
 
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
+PEAK_BF16_MFMA = 2500.0  # TFLOP/s, MI355X dense BF16 matrix
 PEAK_HBM = 8000.0  # GB/s
 ALPHAS = (0.0, 0.25, 0.5, 0.75, 1.0)
 METRIC = "1080p frames/s (flow+consistency) at stated EPE vs FP64 oracle; p99 frame ms"
@@ -101,6 +104,53 @@ def blas_threads():
     return os.cpu_count()
 
 
+def measure(tcflow, desc, blob, precision, I, P, K, W, frames):
+    """Throughput run (K timed steps after W warm-up steps) and latency run of
+    the streaming path at one precision.  Returns a dict of results."""
+    H, W_ = desc["height"], desc["width"]
+    net = tcflow.Net(desc, blob, precision=precision)
+    st = tcflow.StreamState(net, 1, H, W_, device=I[0].device)
+
+    def step(t, events=None):
+        f = frame_index(t, frames)
+        st.push(I[f], P[f], ALPHAS[t % len(ALPHAS)], inputs_ready=True, events=events)
+
+    for t in range(W + 1):  # step 0 only sets O_1 = P_1
+        step(t)
+    torch.cuda.synchronize()
+
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    probe_stage = tcflow.stage_id(1, tcflow.TC_OP_C1)
+    probe = tcflow.Probe(probe_stage, K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        step(W + 1 + i, events=(ev0[i], ev1[i]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n_probe, probe_ms = probe.read()
+    probe.close()
+    wall = t1 - t0
+    gaps = np.diff(np.array([ev1[0].elapsed_time(e) for e in ev1]))
+
+    # latency mode: one frame at a time, as a live stream sees it (the frame's
+    # first kernel to its output, nothing else in flight)
+    NL = min(60, K)
+    lev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(NL)]
+    probe = tcflow.Probe(probe_stage, NL)
+    for i in range(NL):
+        step(W + 1 + K + i, events=lev[i])
+        torch.cuda.synchronize()
+    n_alone, alone_ms = probe.read()
+    probe.close()
+    lat = np.array([a.elapsed_time(b) for a, b in lev])
+    return dict(net=net, fps=K / wall, ms=1e3 * wall / K, lat=lat, gaps=gaps, NL=NL,
+                c1_ms=probe_ms / max(1, n_probe), n_probe=n_probe,
+                c1_alone_ms=alone_ms / max(1, n_alone))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +159,8 @@ def main():
     ap.add_argument("--frames", type=int, default=60)
     ap.add_argument("--cpu-frames", type=int, default=2,
                     help="frames of the workload the FP64 oracle is timed on (0 = skip)")
+    ap.add_argument("--forms", default="bf16",
+                    help="comma-separated precision forms measured after the FP32 path ('' = none)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="before timing, run 3 plain device copies of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -126,7 +178,6 @@ def main():
     desc = synth.load_desc("fullhd")
     H, W = desc["height"], desc["width"]
     blob = synth.he_weights(desc)
-    net = tcflow.Net(desc, blob)
 
     log(f"generating {args.frames} frames {W}x{H} on the GPU")
     scene = synth.LayeredScene(W, H, seed=0)
@@ -142,61 +193,21 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    st = tcflow.StreamState(net, 1, H, W, device=dev)
-
-    def step(t, events=None):
-        f = frame_index(t, args.frames)
-        st.push(I[f], P[f], ALPHAS[t % len(ALPHAS)], inputs_ready=True, events=events)
-
-    log(f"warmup {args.warmup} steps")
-    for t in range(args.warmup + 1):  # step 0 only sets O_1 = P_1
-        step(t)
-    torch.cuda.synchronize()
-
     K = args.steps
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    probe_stage = tcflow.stage_id(1, tcflow.TC_OP_C1)
-    probe = tcflow.Probe(probe_stage, K)
-    log(f"timing {K} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(K):
-        step(args.warmup + 1 + i, events=(ev0[i], ev1[i]))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    n_probe, probe_ms = probe.read()
-    probe.close()
-    wall = t1 - t0
-    fps = K / wall
-    gaps = np.diff(np.array([ev1[0].elapsed_time(e) for e in ev1]))
-
-    # latency mode: one frame at a time, as a live stream sees it (the frame's
-    # first kernel to its output, nothing else in flight)
-    NL = min(60, K)
-    lev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(NL)]
-    probe = tcflow.Probe(probe_stage, NL)
-    for i in range(NL):
-        step(args.warmup + 1 + K + i, events=lev[i])
-        torch.cuda.synchronize()
-    n_alone, alone_ms = probe.read()
-    probe.close()
-    lat = np.array([a.elapsed_time(b) for a, b in lev])
-    log(f"{fps:.1f} frames/s, {1e3 * wall / K:.3f} ms/frame")
-
-    c1_avg_ms = probe_ms / max(1, n_probe)
-    c1_tflops = c1_flops(desc, H, W) / (c1_avg_ms * 1e-3) / 1e12
+    log(f"fp32: warmup {args.warmup}, timing {K} steps")
+    r = measure(tcflow, desc, blob, tcflow.TC_FP32, I, P, K, args.warmup, args.frames)
+    log(f"fp32: {r['fps']:.1f} frames/s, {r['ms']:.3f} ms/frame")
+    c1_tflops = c1_flops(desc, H, W) / (r["c1_ms"] * 1e-3) / 1e12
     t_star = frame_lower_bound_ms(desc, H, W, PEAK_FP32_MFMA)
 
     result = {
         "metric": METRIC,
-        "value": round(fps, 2),
+        "value": round(r["fps"], 2),
         "unit": "frames/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * wall / K, 4),
+        "ms_per_step": round(r["ms"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -212,14 +223,13 @@ def main():
             "alpha_sweep": list(ALPHAS),
             "precision": "fp32",
         },
-        "p50_frame_ms": round(float(np.percentile(lat, 50)), 4),
-        "p99_frame_ms": round(float(np.percentile(lat, 99)), 4),
-        "frame_ms_definition": f"latency of one frame pushed alone ({NL} frames): its first kernel "
-                               "(pyramid) to O_t ready",
-        "p50_output_interval_ms": round(float(np.percentile(gaps, 50)), 4),
-        "p99_output_interval_ms": round(float(np.percentile(gaps, 99)), 4),
-        "frame_roofline": {"t_star_ms": round(t_star, 4),
-                           "frac": round(t_star / (1e3 * wall / K), 4)},
+        "p50_frame_ms": round(float(np.percentile(r["lat"], 50)), 4),
+        "p99_frame_ms": round(float(np.percentile(r["lat"], 99)), 4),
+        "frame_ms_definition": f"latency of one frame pushed alone ({r['NL']} frames): its first "
+                               "kernel (pyramid) to O_t ready",
+        "p50_output_interval_ms": round(float(np.percentile(r["gaps"], 50)), 4),
+        "p99_output_interval_ms": round(float(np.percentile(r["gaps"], 99)), 4),
+        "frame_roofline": {"t_star_ms": round(t_star, 4), "frac": round(t_star / r["ms"], 4)},
         "roofline": {
             "kernel": "conv3x3_f32_mfma (level-1 decoder conv1, fw+bw batch)",
             "bound": "mfma",
@@ -228,32 +238,63 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(c1_tflops / PEAK_FP32_MFMA, 4),
             "traffic": None,
-            "avg_launch_ms": round(c1_avg_ms, 5),
-            "launches": n_probe,
+            "avg_launch_ms": round(r["c1_ms"], 5),
+            "launches": r["n_probe"],
             "note": "launches timed inside the throughput run, where two frames' decoders "
                     "share the GPU; alone_* = the same kernel in the latency pass",
-            "alone_avg_launch_ms": round(alone_ms / max(1, n_alone), 5),
-            "alone_achieved": round(c1_flops(desc, H, W) / (alone_ms / max(1, n_alone) * 1e-3) / 1e12, 2),
+            "alone_avg_launch_ms": round(r["c1_alone_ms"], 5),
+            "alone_achieved": round(c1_flops(desc, H, W) / (r["c1_alone_ms"] * 1e-3) / 1e12, 2),
         },
     }
 
+    forms = {}
+    nets = {"fp32": r["net"]}
+    for form in [f for f in args.forms.split(",") if f]:
+        prec = {"bf16": tcflow.TC_BF16}[form]
+        log(f"{form}: timing {K} steps")
+        rf = measure(tcflow, desc, blob, prec, I, P, K, args.warmup, args.frames)
+        log(f"{form}: {rf['fps']:.1f} frames/s, {rf['ms']:.3f} ms/frame")
+        nets[form] = rf["net"]
+        peak = PEAK_BF16_MFMA
+        ach = c1_flops(desc, H, W) / (rf["c1_alone_ms"] * 1e-3) / 1e12
+        forms[form] = {
+            "value": round(rf["fps"], 2), "unit": "frames/s", "ms_per_step": round(rf["ms"], 4),
+            "speedup_vs_fp32": round(rf["fps"] / r["fps"], 3),
+            "p50_frame_ms": round(float(np.percentile(rf["lat"], 50)), 4),
+            "p99_frame_ms": round(float(np.percentile(rf["lat"], 99)), 4),
+            "frame_roofline": {"t_star_ms": round(frame_lower_bound_ms(desc, H, W, peak, bpe=2), 4),
+                               "frac": round(frame_lower_bound_ms(desc, H, W, peak, bpe=2) / rf["ms"], 4)},
+            "conv1_level1": {"avg_launch_ms": round(rf["c1_ms"], 5),
+                             "alone_avg_launch_ms": round(rf["c1_alone_ms"], 5),
+                             "alone_achieved_tflops": round(ach, 2), "peak_tflops": peak,
+                             "alone_frac": round(ach / peak, 4)},
+        }
+    if forms:
+        result["precision_forms"] = forms
+
     if args.cpu_frames > 0:
-        result["cpu_baseline"], result["epe_vs_oracle"] = cpu_leg(net, desc, I, P, args.cpu_frames)
+        result["cpu_baseline"], epe = cpu_leg(nets, desc, I, P, args.cpu_frames)
+        result["epe_vs_oracle"] = epe.pop("fp32")
+        for form, e in epe.items():
+            result["precision_forms"][form]["epe_vs_oracle"] = e
     print(json.dumps(result), flush=True)
 
 
-def cpu_leg(net, desc, I, P, nframes):
+def cpu_leg(nets, desc, I, P, nframes):
     """Time the FP64 oracle on `nframes` frames of the same workload (flow
-    pair + consistency step with O_{t-1} = P_{t-1}) and compare the GPU's
-    flows, and its consistency step on the oracle's flows, with the oracle."""
+    pair + consistency step with O_{t-1} = P_{t-1}) and compare each GPU
+    form's flows, and its consistency step on the oracle's flows, with it."""
     from oracle import tcflow_oracle as O
     from paper_2301_00750_amd import tcflow
 
     wts = O.unpack_weights(synth.he_weights(desc), desc)
-    epes, maxes, oerr = [], [], []
+    stats = {k: {"epe": [], "max": []} for k in nets}
+    oerr = []
     cpu_s = 0.0
     for t in range(1, nframes + 1):
-        fw, bw = net.flow_estimate_pair(I[t - 1], I[t])
+        gpu = {}
+        for k, net in nets.items():
+            gpu[k] = net.flow_estimate_pair(I[t - 1], I[t])
         torch.cuda.synchronize()
         a64, b64 = I[t - 1][0].double().cpu().numpy(), I[t][0].double().cpu().numpy()
         p64, q64 = P[t][0].double().cpu().numpy(), P[t - 1][0].double().cpu().numpy()
@@ -262,13 +303,15 @@ def cpu_leg(net, desc, I, P, nframes):
         rfw, rbw = O.flow_pair(a64, b64, wts, desc)
         O.consistency(p64, q64, rfw, rbw, 0.5)
         cpu_s += time.perf_counter() - c0
-        for g, r in ((fw, rfw), (bw, rbw)):
-            d = g[0].double().cpu().numpy() - r
-            e = np.sqrt((d ** 2).sum(0))
-            epes.append(float(e.mean()))
-            maxes.append(float(e.max()))
+        for k, (fw, bw) in gpu.items():
+            for g, r in ((fw, rfw), (bw, rbw)):
+                d = g[0].double().cpu().numpy() - r
+                e = np.sqrt((d ** 2).sum(0))
+                stats[k]["epe"].append(float(e.mean()))
+                stats[k]["max"].append(float(e.max()))
         # the GPU consistency step on the oracle's flows (rounded to float32)
-        f32 = [torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32))[None].to(fw.device)
+        dev = I[0].device
+        f32 = [torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32))[None].to(dev)
                for x in (rfw, rbw)]
         go = tcflow.consistency_step(P[t], P[t - 1], f32[0], f32[1], 0.5)
         ro, _, margin, _ = O.consistency(p64, q64, rfw.astype(np.float32).astype(np.float64),
@@ -283,8 +326,11 @@ def cpu_leg(net, desc, I, P, nframes):
         "sample": f"{nframes} frames of the 1920x1080 workload: FP64 flow pair (both pyramids) "
                   f"+ consistency step, {cpu_s:.1f} s",
     }
-    epe = {"mean_px": max(epes), "max_px": max(maxes), "frames": nframes,
-           "consistency_max_abs": max(oerr), "tolerance_mean_px": 0.05}
+    epe = {}
+    for k, s_ in stats.items():
+        epe[k] = {"mean_px": max(s_["epe"]), "max_px": max(s_["max"]), "frames": nframes,
+                  "tolerance_mean_px": 0.05 if k == "fp32" else 0.25}
+    epe["fp32"]["consistency_max_abs"] = max(oerr)
     return base, epe
 
 

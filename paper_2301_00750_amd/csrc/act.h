@@ -1,0 +1,53 @@
+// Device helpers for activation storage: float32 or bfloat16 (stored as the
+// upper 16 bits of a float, round-to-nearest-even), blocks of 8 channels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace tc {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16;  // storage type of bfloat16 activations
+
+__device__ inline float bf2f(bf16 h) { return __uint_as_float((unsigned)h << 16); }
+
+// float -> bfloat16, round to nearest even on the bit pattern; NaN stays NaN.
+__device__ inline bf16 f2bf(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16)(u >> 16);
+}
+
+__device__ inline unsigned pack2(float a, float b) {
+  return (unsigned)f2bf(a) | ((unsigned)f2bf(b) << 16);
+}
+
+__device__ inline void load8(const float* p, float (&v)[8]) {
+  const f4 a = reinterpret_cast<const f4*>(p)[0], b = reinterpret_cast<const f4*>(p)[1];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+__device__ inline void load8(const bf16* p, float (&v)[8]) {
+  const u4 x = *reinterpret_cast<const u4*>(p);
+  v[0] = __uint_as_float(x.x << 16); v[1] = __uint_as_float(x.x & 0xffff0000u);
+  v[2] = __uint_as_float(x.y << 16); v[3] = __uint_as_float(x.y & 0xffff0000u);
+  v[4] = __uint_as_float(x.z << 16); v[5] = __uint_as_float(x.z & 0xffff0000u);
+  v[6] = __uint_as_float(x.w << 16); v[7] = __uint_as_float(x.w & 0xffff0000u);
+}
+
+__device__ inline void store8(float* p, const float (&v)[8]) {
+  reinterpret_cast<f4*>(p)[0] = f4{v[0], v[1], v[2], v[3]};
+  reinterpret_cast<f4*>(p)[1] = f4{v[4], v[5], v[6], v[7]};
+}
+
+__device__ inline void store8(bf16* p, const float (&v)[8]) {
+  *reinterpret_cast<u4*>(p) =
+      u4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
+}
+
+__device__ inline void store1(float* p, float v) { *p = v; }
+__device__ inline void store1(bf16* p, float v) { *p = f2bf(v); }
+
+}  // namespace tc

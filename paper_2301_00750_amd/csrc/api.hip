@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -14,6 +15,8 @@ using namespace tc;
 struct tc_net {
   tc_net_desc d;
   int precision;
+  int bf16act;      // activations stored as bfloat16, convs on BF16 MFMA
+  int esz;          // bytes per stored activation element
   int ncv;          // (2r+1)^2
   int zcb;          // blocks of the cost-volume buffer (ncv + 2, rounded up to 8)
   ConvLayer pyr[8][2];
@@ -92,8 +95,12 @@ struct PyrLayout {
   size_t stage, tmp, partial, total;
 };
 
+int layer_chunks(const ConvLayer& L) {
+  return L.bf16 ? cdiv(L.cin_pad / 8, BF_CPC) : L.cin_pad / L.kc;
+}
+
 size_t layer_partial_bytes(const ConvLayer& L, int out_h, int out_w, int n, int stride) {
-  const ConvPlan p = plan_conv(out_h, out_w, n, L.cin_pad / L.kc, stride, L.np);
+  const ConvPlan p = plan_conv(out_h, out_w, n, layer_chunks(L), stride, L.np);
   return conv_partial_bytes(p, out_h, out_w, n, L.np);
 }
 
@@ -103,7 +110,7 @@ PyrLayout pyr_layout(const tc_net* net, int n, int h, int w) {
   LevelDims g = dims(d, h, w);
   size_t pos = 0, tmp = 0, part = 0;
   for (int l = 1; l <= d.levels; ++l) {
-    const size_t bytes = (size_t)n * d.ch[l - 1] * g.h[l] * g.w[l] * sizeof(float);
+    const size_t bytes = (size_t)n * d.ch[l - 1] * g.h[l] * g.w[l] * net->esz;
     p.off[l] = pos;
     pos = align_up(pos + bytes, kAlign);
     if (bytes > tmp) tmp = bytes;
@@ -113,7 +120,8 @@ PyrLayout pyr_layout(const tc_net* net, int n, int h, int w) {
     }
   }
   p.stage = pos;
-  pos = align_up(pos + (size_t)n * g.hp * g.wp * 4 * sizeof(float), kAlign);
+  // staged frame: float blocks of 4 or bfloat16 blocks of 8, 16 bytes per pixel
+  pos = align_up(pos + (size_t)n * g.hp * g.wp * 16, kAlign);
   p.tmp = pos;
   pos = align_up(pos + tmp, kAlign);
   p.partial = pos;
@@ -140,9 +148,9 @@ DecLayout dec_layout(const tc_net* net, int nb, int h, int w) {
   L.flow[0] = take(px * 2 * sizeof(float));
   L.flow[1] = take(px * 2 * sizeof(float));
   L.U = take(px * 2 * sizeof(float));
-  L.Z = take(px * net->zcb * 8 * sizeof(float));
-  L.H1 = take(px * net->d.dec[0] * sizeof(float));
-  L.H23 = take(px * (net->d.dec[1] + net->d.dec[2]) * sizeof(float));
+  L.Z = take(px * net->zcb * 8 * net->esz);
+  L.H1 = take(px * net->d.dec[0] * net->esz);
+  L.H23 = take(px * (net->d.dec[1] + net->d.dec[2]) * net->esz);
   size_t part = 0;
   for (int l = 1; l <= net->d.levels; ++l)
     for (int k = 0; k < 3; ++k) {
@@ -178,6 +186,40 @@ void pack_conv(const float* W, const float* b, int cout, int cin, int kc, int ci
   for (int o = 0; o < cout; ++o) bout[o] = b[o];
 }
 
+uint16_t host_f2bf(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Pack W for conv3x3_bf16_mfma: per chunk of BF_CPC input blocks (8 channels
+// each), the 9 * cpc (tap, block) pairs, block fastest, fill MFMA steps of 4
+// lane groups: word [chunk][step][group][n] holds 8 bfloat16 k-values.
+void pack_conv_bf16(const float* W, const float* b, int cout, int cin, int cin_pad,
+                    const std::vector<int>& cmap, std::vector<uint16_t>& wout,
+                    std::vector<float>& bout, int& np) {
+  np = (cout + 15) / 16 * 16;
+  const int nblk = cin_pad / 8, nch = cdiv(nblk, BF_CPC);
+  wout.assign((size_t)nch * BF_STEPS * 4 * np * 8, 0);
+  bout.assign(np, 0.f);
+  for (int c = 0; c < nch; ++c) {
+    const int cpc = std::min(BF_CPC, nblk - c * BF_CPC);
+    for (int kb = 0; kb < 9 * cpc; ++kb) {
+      const int tap = kb / cpc, cbi = kb % cpc, st = kb / 4, g = kb % 4;
+      for (int o = 0; o < cout; ++o)
+        for (int j = 0; j < 8; ++j) {
+          const int src = cmap[(c * BF_CPC + cbi) * 8 + j];
+          if (src < 0) continue;
+          wout[((((size_t)c * BF_STEPS + st) * 4 + g) * np + o) * 8 + j] =
+              host_f2bf(W[((size_t)o * cin + src) * 9 + tap]);
+        }
+    }
+  }
+  for (int o = 0; o < cout; ++o) bout[o] = b[o];
+}
+
 View plain_view(const float* p, int cbt, int cb0 = 0) {
   View v;
   v.a = p;
@@ -191,7 +233,7 @@ View plain_view(const float* p, int cbt, int cb0 = 0) {
 int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, int in_h, int in_w,
                float* out, int out_cbt, int out_cb0, int compact, const float* add, int out_h,
                int out_w, int relu, float slope, int n, int stride, int stage, float* partial,
-               hipStream_t s) {
+               int act_bf16, hipStream_t s) {
   ConvArgs a;
   a.in0 = in0;
   a.in1 = in1;
@@ -207,7 +249,9 @@ int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, in
   a.out_w = out_w;
   a.w = L.w;
   a.b = L.b;
-  a.nchunks = L.cin_pad / L.kc;
+  a.nchunks = layer_chunks(L);
+  a.nblk = L.cin_pad / 8;
+  a.bf16act = L.bf16 ? 1 : 0;
   a.cout = L.cout;
   a.np = L.np;
   a.lrelu = relu;
@@ -218,7 +262,9 @@ int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, in
   probe_begin(stage, s);
   if (L.cout == 2 && compact && stride == 1 && L.kc == 8) {  // estimator head
     a.splits = 1;
+    a.nchunks = L.cin_pad / 8;
     a.cps = a.nchunks;
+    a.bf16act = act_bf16;
     e = launch_head(a, s);
   } else {
     const ConvPlan p = plan_conv(out_h, out_w, n, a.nchunks, stride, L.np);
@@ -239,20 +285,21 @@ int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, cha
   float* tmp = reinterpret_cast<float*>(pyr + p.tmp);
   float* part = reinterpret_cast<float*>(pyr + p.partial);
   probe_begin(TC_STAGE_INPUT, s);
-  TC_TRY_HIP(launch_stage(frames, n, h, w, stage, g.hp, g.wp, s));
+  TC_TRY_HIP(launch_stage(frames, n, h, w, stage, g.hp, g.wp, net->bf16act, s));
   probe_end(TC_STAGE_INPUT, s);
   const float* in = stage;
   int in_cbt = 1, in_h = g.hp, in_w = g.wp;
   for (int l = 1; l <= d.levels; ++l) {
     const int C = d.ch[l - 1];
     float* feat = reinterpret_cast<float*>(pyr + p.off[l]);
-    int st = conv_layer(net->pyr[l - 1][0], plain_view(in, in_cbt), net->pyr[l - 1][0].cin_pad / net->pyr[l - 1][0].kc,
+    const ConvLayer& La = net->pyr[l - 1][0];
+    int st = conv_layer(La, plain_view(in, in_cbt), La.cin_pad / (La.bf16 ? 8 : La.kc),
                         plain_view(in, in_cbt), in_h, in_w, tmp, C / 8, 0, 0, nullptr, g.h[l], g.w[l],
-                        1, d.leaky, n, 2, TC_STAGE(l, TC_OP_PYR_A), part, s);
+                        1, d.leaky, n, 2, TC_STAGE(l, TC_OP_PYR_A), part, net->bf16act, s);
     if (st) return st;
     st = conv_layer(net->pyr[l - 1][1], plain_view(tmp, C / 8), C / 8, plain_view(tmp, C / 8),
                     g.h[l], g.w[l], feat, C / 8, 0, 0, nullptr, g.h[l], g.w[l], 1, d.leaky, n, 1,
-                    TC_STAGE(l, TC_OP_PYR_B), part, s);
+                    TC_STAGE(l, TC_OP_PYR_B), part, net->bf16act, s);
     if (st) return st;
     in = feat;
     in_cbt = C / 8;
@@ -308,22 +355,23 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
     cv.splits = cp.splits;
     cv.cps = cp.cps;
     cv.partial = part;
+    cv.bf16act = net->bf16act;
     probe_begin(TC_STAGE(l, TC_OP_COST_VOLUME), s);
     TC_TRY_HIP(launch_warp_cost_volume(cv, s));
     probe_end(TC_STAGE(l, TC_OP_COST_VOLUME), s);
     const ConvLayer* L = net->dec[l - 1];
     int st = conv_layer(L[0], f1, C / 8, plain_view(Z, net->zcb), hl, wl, H1, d0b, 0, 0, nullptr,
-                        hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C1), part, s);
+                        hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C1), part, net->bf16act, s);
     if (st) return st;
     st = conv_layer(L[1], plain_view(H1, d0b), d0b, plain_view(H1, d0b), hl, wl, H23, d23b, 0, 0,
-                    nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C2), part, s);
+                    nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C2), part, net->bf16act, s);
     if (st) return st;
     st = conv_layer(L[2], plain_view(H23, d23b), d1b, plain_view(H23, d23b), hl, wl, H23, d23b,
-                    d1b, 0, nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C3), part, s);
+                    d1b, 0, nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C3), part, net->bf16act, s);
     if (st) return st;
     const int nxt = cur ^ 1;
     st = conv_layer(L[3], plain_view(H23, d23b), d23b, plain_view(H23, d23b), hl, wl, flows[nxt],
-                    0, 0, 1, Ul, hl, wl, 0, 0.f, nb, 1, TC_STAGE(l, TC_OP_HEAD), part, s);
+                    0, 0, 1, Ul, hl, wl, 0, 0.f, nb, 1, TC_STAGE(l, TC_OP_HEAD), part, net->bf16act, s);
     if (st) return st;
     cur = nxt;
   }
@@ -351,7 +399,7 @@ const char* tc_status_str(int st) {
   }
 }
 
-const char* tc_version(void) { return "tcflow 0.1 (gfx950, fp32 MFMA)"; }
+const char* tc_version(void) { return "tcflow 0.2 (gfx950; FP32 and BF16 MFMA)"; }
 
 size_t tc_weight_floats(const tc_net_desc* d) {
   if (!desc_ok(d)) return 0;
@@ -372,31 +420,45 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
                   int precision, tc_net** out) {
   if (!desc || !host_weights || !out) return TC_ERR_INVALID_ARG;
   if (!desc_ok(desc)) return TC_ERR_SHAPE;
-  if (precision != TC_FP32) return TC_ERR_UNSUPPORTED;
+  if (precision != TC_FP32 && precision != TC_BF16) return TC_ERR_UNSUPPORTED;
   if (n_floats != tc_weight_floats(desc)) return TC_ERR_SHAPE;
   tc_net* net = new (std::nothrow) tc_net();
   if (!net) return TC_ERR_HIP;
   net->d = *desc;
   net->precision = precision;
+  net->bf16act = precision == TC_BF16;
+  net->esz = net->bf16act ? 2 : 4;
   net->ncv = (2 * desc->radius + 1) * (2 * desc->radius + 1);
   net->zcb = (net->ncv + 2 + 7) / 8;
   const int L = desc->levels;
 
   // host packing
   struct Packed {
-    std::vector<float> w, b;
+    std::vector<char> w;
+    std::vector<float> b;
   };
   std::vector<Packed> packed;
   std::vector<ConvLayer*> slots;
   const float* src = host_weights;
   auto add_layer = [&](ConvLayer& cl, int cout, int cin, int kc, int cin_pad,
-                       const std::vector<int>& cmap) {
+                       const std::vector<int>& cmap, bool head) {
     const float* W = src;
     const float* b = src + (size_t)cout * cin * 9;
     src += conv_floats(cout, cin);
     Packed pk;
     int np = 0;
-    pack_conv(W, b, cout, cin, kc, cin_pad, cmap, pk.w, pk.b, np);
+    cl.bf16 = net->bf16act && !head;
+    if (cl.bf16) {
+      std::vector<uint16_t> wb;
+      pack_conv_bf16(W, b, cout, cin, cin_pad, cmap, wb, pk.b, np);
+      pk.w.resize(wb.size() * 2);
+      memcpy(pk.w.data(), wb.data(), pk.w.size());
+    } else {
+      std::vector<float> wf;
+      pack_conv(W, b, cout, cin, kc, cin_pad, cmap, wf, pk.b, np);
+      pk.w.resize(wf.size() * 4);
+      memcpy(pk.w.data(), wf.data(), pk.w.size());
+    }
     cl.cin = cin;
     cl.cout = cout;
     cl.cin_pad = cin_pad;
@@ -413,10 +475,11 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
   for (int l = 1; l <= L; ++l) {
     const int C = desc->ch[l - 1];
     const int cin = l == 1 ? 3 : desc->ch[l - 2];
-    const int kc = l == 1 ? 4 : 8;
-    const int pad = l == 1 ? 4 : cin;
-    add_layer(net->pyr[l - 1][0], C, cin, kc, pad, identity(cin, pad));
-    add_layer(net->pyr[l - 1][1], C, C, 8, C, identity(C, C));
+    // the staged frame is one block of 4 (float) or 8 (bfloat16) channels
+    const int kc = (l == 1 && !net->bf16act) ? 4 : 8;
+    const int pad = l == 1 ? kc : cin;
+    add_layer(net->pyr[l - 1][0], C, cin, kc, pad, identity(cin, pad), false);
+    add_layer(net->pyr[l - 1][1], C, C, 8, C, identity(C, C), false);
   }
   const int d0 = desc->dec[0], d1 = desc->dec[1], d2 = desc->dec[2];
   for (int l = 1; l <= L; ++l) {
@@ -429,10 +492,10 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     for (int k = 0; k < net->ncv; ++k) m[C + k] = k;
     m[C + net->ncv] = net->ncv + C;
     m[C + net->ncv + 1] = net->ncv + C + 1;
-    add_layer(net->dec[l - 1][0], d0, net->ncv + C + 2, 8, pad, m);
-    add_layer(net->dec[l - 1][1], d1, d0, 8, d0, identity(d0, d0));
-    add_layer(net->dec[l - 1][2], d2, d1, 8, d1, identity(d1, d1));
-    add_layer(net->dec[l - 1][3], 2, d1 + d2, 8, d1 + d2, identity(d1 + d2, d1 + d2));
+    add_layer(net->dec[l - 1][0], d0, net->ncv + C + 2, 8, pad, m, false);
+    add_layer(net->dec[l - 1][1], d1, d0, 8, d0, identity(d0, d0), false);
+    add_layer(net->dec[l - 1][2], d2, d1, 8, d1, identity(d1, d1), false);
+    add_layer(net->dec[l - 1][3], 2, d1 + d2, 8, d1 + d2, identity(d1 + d2, d1 + d2), true);
   }
 
   // one device allocation for every layer
@@ -440,7 +503,7 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
   std::vector<size_t> offs;
   for (auto& pk : packed) {
     offs.push_back(total);
-    total = align_up(total + pk.w.size() * sizeof(float), kAlign);
+    total = align_up(total + pk.w.size(), kAlign);
     offs.push_back(total);
     total = align_up(total + pk.b.size() * sizeof(float), kAlign);
   }
@@ -450,7 +513,7 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
   }
   std::vector<char> host(total, 0);
   for (size_t i = 0; i < packed.size(); ++i) {
-    memcpy(host.data() + offs[2 * i], packed[i].w.data(), packed[i].w.size() * sizeof(float));
+    memcpy(host.data() + offs[2 * i], packed[i].w.data(), packed[i].w.size());
     memcpy(host.data() + offs[2 * i + 1], packed[i].b.data(), packed[i].b.size() * sizeof(float));
     slots[i]->w = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[2 * i]);
     slots[i]->b = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[2 * i + 1]);

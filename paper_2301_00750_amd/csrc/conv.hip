@@ -16,12 +16,13 @@
 //   A (16 x 4):  A[m = l % 16][k = l / 16]
 //   B (4 x 16):  B[k = l / 16][n = l % 16]
 //   D (16 x 16): D[m = 4 * (l / 16) + v][n = l % 16] in accumulator VGPR v.
+#include "act.h"
 #include "tc_internal.h"
 
 namespace tc {
 namespace {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int TW = 16;
 
@@ -34,6 +35,12 @@ __device__ inline const float* view_base(const View& v, int img, size_t img_floa
                         : v.b + (size_t)(img - v.nsplit) * img_floats;
 }
 
+template <typename T>
+__device__ inline const T* view_base_t(const View& v, int img, size_t img_elems) {
+  return img < v.nsplit ? reinterpret_cast<const T*>(v.a) + (size_t)img * img_elems
+                        : reinterpret_cast<const T*>(v.b) + (size_t)(img - v.nsplit) * img_elems;
+}
+
 __device__ inline float finish(const ConvArgs& a, float v, int n, size_t pix) {
   v += a.b[n];
   if (a.lrelu) v = v >= 0.f ? v : a.slope * v;
@@ -41,14 +48,17 @@ __device__ inline float finish(const ConvArgs& a, float v, int n, size_t pix) {
   return v;
 }
 
+// Compact outputs (flows) are always float; blocked activations are T.
+template <typename T>
 __device__ inline void store_out(const ConvArgs& a, float v, int img, int oy, int ox, int n) {
   const size_t pix = ((size_t)img * a.out_h + oy) * a.out_w + ox;
   if (a.compact) {
     a.out[pix * a.cout + n] = v;
   } else {
     const size_t plane = (size_t)a.out_h * a.out_w * 8;
-    a.out[(size_t)img * a.out_cbt * plane + (size_t)(a.out_cb0 + (n >> 3)) * plane +
-          ((size_t)oy * a.out_w + ox) * 8 + (n & 7)] = v;
+    store1(reinterpret_cast<T*>(a.out) + (size_t)img * a.out_cbt * plane +
+               (size_t)(a.out_cb0 + (n >> 3)) * plane + ((size_t)oy * a.out_w + ox) * 8 + (n & 7),
+           v);
   }
 }
 
@@ -183,7 +193,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_mfma(ConvArgs a) {
               acc[mb][nb][vv];
         } else {
           const size_t pix = ((size_t)img * a.out_h + oy) * a.out_w + ox;
-          store_out(a, finish(a, acc[mb][nb][vv], n, pix), img, oy, ox, n);
+          store_out<float>(a, finish(a, acc[mb][nb][vv], n, pix), img, oy, ox, n);
         }
       }
     }
@@ -191,6 +201,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_mfma(ConvArgs a) {
 }
 
 // Sum of the split-K partials in split order, then bias / LeakyReLU / add / store.
+template <typename T>
 __global__ __launch_bounds__(256) void conv_reduce_kernel(ConvArgs a) {
   const size_t pixels = (size_t)a.n * a.out_h * a.out_w;
   const size_t total = pixels * a.cout;
@@ -203,7 +214,7 @@ __global__ __launch_bounds__(256) void conv_reduce_kernel(ConvArgs a) {
     const int ox = (int)(pix % a.out_w);
     const int oy = (int)((pix / a.out_w) % a.out_h);
     const int img = (int)(pix / ((size_t)a.out_w * a.out_h));
-    store_out(a, finish(a, s, n, pix), img, oy, ox, n);
+    store_out<T>(a, finish(a, s, n, pix), img, oy, ox, n);
   }
 }
 
@@ -217,6 +228,7 @@ __global__ __launch_bounds__(256) void conv_reduce_kernel(ConvArgs a) {
 // result does not depend on scheduling or on the batch.
 constexpr int HD_TY = 8, HD_TX = 32, HD_MAXCH = 16;
 
+template <typename T>
 __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
   constexpr int HY = HD_TY + 2, HX = HD_TX + 2, NPOS = HY * HX;
   __shared__ f4 s_in[4][2][NPOS];               // per wave: one 8-channel halo tile
@@ -243,15 +255,16 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
     if (active) {
       const View& v = ch < a.nb0 ? a.in0 : a.in1;
       const int cb = (ch < a.nb0 ? ch : ch - a.nb0) + v.cb0;
-      const float* src = view_base(v, img, in_plane * v.cbt) + (size_t)cb * in_plane;
+      const T* src = view_base_t<T>(v, img, in_plane * v.cbt) + (size_t)cb * in_plane;
       for (int p = lane; p < NPOS; p += 64) {
         const int py = p / HX, px = p - py * HX;
         const int gy = ty0 - 1 + py, gx = tx0 - 1 + px;
         f4 lo = f4{0.f, 0.f, 0.f, 0.f}, hi = lo;
         if (gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w) {
-          const f4* q = reinterpret_cast<const f4*>(src + ((size_t)gy * a.in_w + gx) * 8);
-          lo = q[0];
-          hi = q[1];
+          float vv[8];
+          load8(src + ((size_t)gy * a.in_w + gx) * 8, vv);
+          lo = f4{vv[0], vv[1], vv[2], vv[3]};
+          hi = f4{vv[4], vv[5], vv[6], vv[7]};
         }
         s_in[wave][0][p] = lo;
         s_in[wave][1][p] = hi;
@@ -298,8 +311,161 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
     r1 += s_red[(w * 256 + tid) * 2 + 1];
   }
   const size_t pix = ((size_t)img * a.out_h + y) * a.out_w + x;
-  store_out(a, finish(a, r0, 0, pix), img, y, x, 0);
-  store_out(a, finish(a, r1, 1, pix), img, y, x, 1);
+  store_out<float>(a, finish(a, r0, 0, pix), img, y, x, 0);
+  store_out<float>(a, finish(a, r1, 1, pix), img, y, x, 1);
+}
+
+// ---------------------------------------------------------------- BF16 conv
+//
+// v_mfma_f32_16x16x32_bf16: lane l supplies 8 consecutive K values,
+//   A[m = l % 16][k = 8 * (l / 16) .. + 7],  B[k = 8 * (l / 16) .. + 7][n = l % 16],
+//   D as for the FP32 16x16 MFMA.
+// K is walked in blocks of 8 input channels; a chunk holds BF_CPC channel
+// blocks and its 9 * BF_CPC (tap, block) pairs, block fastest, are dealt to the
+// four lane groups of consecutive MFMA steps, so a step can span two taps and
+// no tap is padded to 32 channels.  The weights of a chunk are packed
+// [step][lane group][n][8 k] so one 16-byte LDS read is one B fragment.
+template <int S, int NB, int MR>
+__global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
+  constexpr int TH = 4 * MR;
+  constexpr int IH = (TH - 1) * S + 3, IW = (TW - 1) * S + 3;
+  constexpr int NPOS = IH * IW;
+  constexpr int NP = NB * 16;
+  constexpr int NA = BF_CPC * NPOS;        // 16-byte words of input per chunk
+  constexpr int NBW = BF_STEPS * 4 * NP;   // 16-byte words of weights per chunk
+  constexpr int RA = (NA + 255) / 256, RB = (NBW + 255) / 256;
+  __shared__ u4 sA[NA];
+  __shared__ u4 sB[NBW];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int tx0 = blockIdx.x * TW, ty0 = blockIdx.y * TH;
+  const int img = blockIdx.z / a.splits, split = blockIdx.z - img * a.splits;
+  const int iy0 = ty0 * S - 1, ix0 = tx0 * S - 1;
+  const size_t in_plane = (size_t)a.in_h * a.in_w * 8;
+  const int c_begin = split * a.cps;
+  const int c_end = min(a.nchunks, c_begin + a.cps);
+  const int nblk = a.nblk;
+
+  f4 acc[MR][NB];
+#pragma unroll
+  for (int i = 0; i < MR; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  u4 ra[RA], rb[RB];
+  auto fetch = [&](int ch) {
+#pragma unroll
+    for (int j = 0; j < RA; ++j) {
+      const int i = tid + j * 256;
+      u4 val = u4{0u, 0u, 0u, 0u};
+      if (i < NA) {
+        const int cbi = i / NPOS, pos = i - cbi * NPOS;
+        const int b = ch * BF_CPC + cbi;
+        const int py = pos / IW, px = pos - py * IW;
+        const int gy = iy0 + py, gx = ix0 + px;
+        if (b < nblk && gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w) {
+          const View& v = b < a.nb0 ? a.in0 : a.in1;
+          const int cb = (b < a.nb0 ? b : b - a.nb0) + v.cb0;
+          const bf16* src = view_base_t<bf16>(v, img, in_plane * v.cbt) + (size_t)cb * in_plane;
+          val = *reinterpret_cast<const u4*>(src + ((size_t)gy * a.in_w + gx) * 8);
+        }
+      }
+      ra[j] = val;
+    }
+    const u4* wsrc = reinterpret_cast<const u4*>(a.w) + (size_t)ch * NBW;
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int i = tid + j * 256;
+      rb[j] = i < NBW ? wsrc[i] : u4{0u, 0u, 0u, 0u};
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int j = 0; j < RA; ++j) {
+      const int i = tid + j * 256;
+      if (i < NA) sA[i] = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int i = tid + j * 256;
+      if (i < NBW) sB[i] = rb[j];
+    }
+  };
+
+  const int lm = lane & 15, lk = lane >> 4;
+  if (c_begin < c_end) fetch(c_begin);
+  for (int ch = c_begin; ch < c_end; ++ch) {
+    stash();
+    __syncthreads();
+    if (ch + 1 < c_end) fetch(ch + 1);
+    const int cpc = min(BF_CPC, nblk - ch * BF_CPC);
+    const int nk = 9 * cpc;
+    const int steps = (nk + 3) / 4;
+#pragma unroll
+    for (int st = 0; st < BF_STEPS; ++st) {
+      if (st < steps) {
+        const int kb = 4 * st + lk;
+        const bool ok = kb < nk;
+        const int tap = ok ? kb / cpc : 0, cbi = ok ? kb - (kb / cpc) * cpc : 0;
+        const int p = tap / 3, q = tap - (tap / 3) * 3;
+        bf8 fb[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          fb[nb] = __builtin_bit_cast(bf8, sB[(st * 4 + lk) * NP + nb * 16 + lm]);
+#pragma unroll
+        for (int mb = 0; mb < MR; ++mb) {
+          const int r = wave * MR + mb;
+          const bf8 fa =
+              __builtin_bit_cast(bf8, sA[cbi * NPOS + (r * S + p) * IW + lm * S + q]);
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[nb], acc[mb][nb], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int mb = 0; mb < MR; ++mb) {
+    const int oy = ty0 + wave * MR + mb;
+    if (oy >= a.out_h) continue;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int n = nb * 16 + lm;
+      if (n >= a.cout) continue;
+#pragma unroll
+      for (int vv = 0; vv < 4; ++vv) {
+        const int ox = tx0 + 4 * lk + vv;
+        if (ox >= a.out_w) continue;
+        if (a.splits > 1) {
+          a.partial[((((size_t)split * a.n + img) * a.out_h + oy) * a.out_w + ox) * NP + n] =
+              acc[mb][nb][vv];
+        } else {
+          const size_t pix = ((size_t)img * a.out_h + oy) * a.out_w + ox;
+          store_out<bf16>(a, finish(a, acc[mb][nb][vv], n, pix), img, oy, ox, n);
+        }
+      }
+    }
+  }
+}
+
+template <int S, int MR>
+hipError_t dispatch_bf16(const ConvArgs& a, hipStream_t s) {
+  dim3 grid(cdiv(a.out_w, TW), cdiv(a.out_h, 4 * MR), a.n * a.splits);
+  switch (a.np / 16) {
+    case 1: conv3x3_bf16_mfma<S, 1, MR><<<grid, 256, 0, s>>>(a); break;
+    case 2: conv3x3_bf16_mfma<S, 2, MR><<<grid, 256, 0, s>>>(a); break;
+    case 3: conv3x3_bf16_mfma<S, 3, MR><<<grid, 256, 0, s>>>(a); break;
+    case 4: conv3x3_bf16_mfma<S, 4, MR><<<grid, 256, 0, s>>>(a); break;
+    case 5: conv3x3_bf16_mfma<S, 5, MR><<<grid, 256, 0, s>>>(a); break;
+    case 6: conv3x3_bf16_mfma<S, 6, MR><<<grid, 256, 0, s>>>(a); break;
+    case 7: conv3x3_bf16_mfma<S, 7, MR><<<grid, 256, 0, s>>>(a); break;
+    case 8: conv3x3_bf16_mfma<S, 8, MR><<<grid, 256, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <int S, int KC, int MR>
@@ -359,14 +525,21 @@ hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, int mr, hipStre
   if (a.n <= 0 || a.out_h <= 0 || a.out_w <= 0) return hipSuccess;
   if (a.splits < 1 || a.cps < 1 || (a.splits > 1 && !a.partial)) return hipErrorInvalidValue;
   hipError_t e = hipErrorInvalidValue;
-  if (stride == 1 && kc == 8 && mr == 4) e = dispatch_nb<1, 8, 4>(a, s);
+  if (a.bf16act) {
+    if (stride == 1 && mr == 4) e = dispatch_bf16<1, 4>(a, s);
+    else if (stride == 1 && mr == 2) e = dispatch_bf16<1, 2>(a, s);
+    else if (stride == 2 && mr == 2) e = dispatch_bf16<2, 2>(a, s);
+  } else if (stride == 1 && kc == 8 && mr == 4) e = dispatch_nb<1, 8, 4>(a, s);
   else if (stride == 1 && kc == 8 && mr == 2) e = dispatch_nb<1, 8, 2>(a, s);
   else if (stride == 2 && kc == 8 && mr == 2) e = dispatch_nb<2, 8, 2>(a, s);
   else if (stride == 2 && kc == 4 && mr == 2) e = dispatch_nb<2, 4, 2>(a, s);
   else if (stride == 1 && kc == 4 && mr == 2) e = dispatch_nb<1, 4, 2>(a, s);
   if (e != hipSuccess || a.splits == 1) return e;
   const size_t total = (size_t)a.n * a.out_h * a.out_w * a.cout;
-  conv_reduce_kernel<<<grid_1d(total), 256, 0, s>>>(a);
+  if (a.bf16act)
+    conv_reduce_kernel<bf16><<<grid_1d(total), 256, 0, s>>>(a);
+  else
+    conv_reduce_kernel<float><<<grid_1d(total), 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -374,7 +547,10 @@ hipError_t launch_head(const ConvArgs& a, hipStream_t s) {
   if (a.n <= 0 || a.out_h <= 0 || a.out_w <= 0) return hipSuccess;
   if (a.cout != 2 || a.np != 16 || a.nchunks > HD_MAXCH) return hipErrorInvalidValue;
   dim3 grid(cdiv(a.out_w, HD_TX), cdiv(a.out_h, HD_TY), a.n);
-  head_kernel<<<grid, 256, 0, s>>>(a);
+  if (a.bf16act)
+    head_kernel<bf16><<<grid, 256, 0, s>>>(a);
+  else
+    head_kernel<float><<<grid, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

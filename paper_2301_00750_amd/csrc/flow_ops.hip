@@ -1,16 +1,17 @@
 // Bandwidth-bound steps of the flow network: frame staging, flow upsampling,
 // the fused feature warp + cost volume, and the final upsample-and-crop.
+#include "act.h"
 #include "tc_internal.h"
 
 namespace tc {
 namespace {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-
 // ---------------------------------------------------------------- staging
 
+// T = float: blocks of 4 channels (RGB, 0); T = bf16: blocks of 8 (RGB, 0 x 5).
+template <typename T>
 __global__ __launch_bounds__(256) void stage_kernel(const float* __restrict__ frames, int n, int h,
-                                                    int w, float* __restrict__ out, int hp, int wp) {
+                                                    int w, T* __restrict__ out, int hp, int wp) {
   const size_t total = (size_t)n * hp * wp;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
        i += (size_t)gridDim.x * blockDim.x) {
@@ -20,7 +21,12 @@ __global__ __launch_bounds__(256) void stage_kernel(const float* __restrict__ fr
     const int sy = y < h ? y : h - 1, sx = x < w ? x : w - 1;
     const size_t plane = (size_t)h * w;
     const float* f = frames + (size_t)img * 3 * plane + (size_t)sy * w + sx;
-    *reinterpret_cast<f4*>(out + i * 4) = f4{f[0], f[plane], f[2 * plane], 0.f};
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<f4*>(out + i * 4) = f4{f[0], f[plane], f[2 * plane], 0.f};
+    } else {
+      const float v[8] = {f[0], f[plane], f[2 * plane], 0.f, 0.f, 0.f, 0.f, 0.f};
+      store8(out + i * 8, v);
+    }
   }
 }
 
@@ -93,12 +99,13 @@ __global__ __launch_bounds__(256) void final_flow_kernel(const float* __restrict
 
 constexpr int CV_TY = 8, CV_TX = 32;
 
-__device__ inline const float* vbase(const View& v, int img, size_t img_floats) {
-  return img < v.nsplit ? v.a + (size_t)img * img_floats
-                        : v.b + (size_t)(img - v.nsplit) * img_floats;
+template <typename T>
+__device__ inline const T* vbase(const View& v, int img, size_t img_elems) {
+  return img < v.nsplit ? reinterpret_cast<const T*>(v.a) + (size_t)img * img_elems
+                        : reinterpret_cast<const T*>(v.b) + (size_t)(img - v.nsplit) * img_elems;
 }
 
-template <int R>
+template <int R, typename T>
 __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
   constexpr int D = 2 * R + 1, NCV = D * D;
   constexpr int HY = CV_TY + 2 * R, HX = CV_TX + 2 * R, NPOS = HY * HX;
@@ -114,8 +121,8 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
   const size_t plane = (size_t)h * w * 8;
   const int cb_begin = split * a.cps;
   const int cb_end = min(a.C / 8, cb_begin + a.cps);
-  const float* f1 = vbase(a.f1, img, plane * a.f1.cbt);
-  const float* f2 = vbase(a.f2, img, plane * a.f2.cbt);
+  const T* f1 = vbase<T>(a.f1, img, plane * a.f1.cbt);
+  const T* f2 = vbase<T>(a.f2, img, plane * a.f2.cbt);
   const float2* U = a.U ? reinterpret_cast<const float2*>(a.U) + (size_t)img * h * w : nullptr;
 
   float acc[NCV];
@@ -123,16 +130,17 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
   for (int k = 0; k < NCV; ++k) acc[k] = 0.f;
 
   for (int cb = cb_begin; cb < cb_end; ++cb) {
-    const float* f2c = f2 + (size_t)cb * plane;
+    const T* f2c = f2 + (size_t)cb * plane;
     for (int p = tid; p < NPOS; p += 256) {
       const int py = p / HX, px = p - py * HX;
       const int Y = ty0 - R + py, X = tx0 - R + px;
       f4 lo = f4{0.f, 0.f, 0.f, 0.f}, hi = lo;
       if (Y >= 0 && Y < h && X >= 0 && X < w) {
         if (!U) {
-          const f4* s = reinterpret_cast<const f4*>(f2c + ((size_t)Y * w + X) * 8);
-          lo = s[0];
-          hi = s[1];
+          float v[8];
+          load8(f2c + ((size_t)Y * w + X) * 8, v);
+          lo = f4{v[0], v[1], v[2], v[3]};
+          hi = f4{v[4], v[5], v[6], v[7]};
         } else {
           const float2 u = U[(size_t)Y * w + X];
           const float fx = floorf(u.x), fy = floorf(u.y);
@@ -143,9 +151,10 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
             const int xi = x0 + (t & 1), yi = y0 + (t >> 1);
             const float wt = ((t & 1) ? ax : 1.f - ax) * ((t >> 1) ? ay : 1.f - ay);
             if (xi >= 0 && xi < w && yi >= 0 && yi < h) {
-              const f4* s = reinterpret_cast<const f4*>(f2c + ((size_t)yi * w + xi) * 8);
-              lo += wt * s[0];
-              hi += wt * s[1];
+              float v[8];
+              load8(f2c + ((size_t)yi * w + xi) * 8, v);
+              lo += wt * f4{v[0], v[1], v[2], v[3]};
+              hi += wt * f4{v[4], v[5], v[6], v[7]};
             }
           }
         }
@@ -155,8 +164,9 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
     }
     __syncthreads();
     if (valid) {
-      const f4* s1 = reinterpret_cast<const f4*>(f1 + (size_t)cb * plane + ((size_t)y * w + x) * 8);
-      const f4 a0 = s1[0], a1 = s1[1];
+      float v1[8];
+      load8(f1 + (size_t)cb * plane + ((size_t)y * w + x) * 8, v1);
+      const f4 a0 = f4{v1[0], v1[1], v1[2], v1[3]}, a1 = f4{v1[4], v1[5], v1[6], v1[7]};
 #pragma unroll
       for (int dy = 0; dy < D; ++dy)
 #pragma unroll
@@ -194,7 +204,7 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
     uy = u.y;
   }
   constexpr int ZCB = (NCV + 2 + 7) / 8;
-  float* z = a.Z + (size_t)img * ZCB * plane + ((size_t)y * w + x) * 8;
+  T* z = reinterpret_cast<T*>(a.Z) + (size_t)img * ZCB * plane + ((size_t)y * w + x) * 8;
 #pragma unroll
   for (int b = 0; b < ZCB; ++b) {
     float v[8];
@@ -212,16 +222,14 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
       }
       v[e] = val;
     }
-    f4* d = reinterpret_cast<f4*>(z + (size_t)b * plane);
-    d[0] = f4{v[0], v[1], v[2], v[3]};
-    d[1] = f4{v[4], v[5], v[6], v[7]};
+    store8(z + (size_t)b * plane, v);
   }
 }
 
 // Adds the channel splits of the cost volume in split order and writes Z:
 // one thread per (pixel, channel of Z), neighbouring threads on neighbouring
 // pixels so the partial reads are coalesced.
-template <int R>
+template <int R, typename T>
 __global__ __launch_bounds__(256) void cv_reduce_kernel(CvArgs a) {
   constexpr int D = 2 * R + 1, NCV = D * D, ZCB = (NCV + 2 + 7) / 8;
   const size_t hw = (size_t)a.h * a.w;
@@ -241,7 +249,8 @@ __global__ __launch_bounds__(256) void cv_reduce_kernel(CvArgs a) {
     } else if (c == NCV || c == NCV + 1) {
       val = a.U ? a.U[((size_t)img * hw + pix) * 2 + (c - NCV)] : 0.f;
     }
-    a.Z[((size_t)img * ZCB + (c >> 3)) * hw * 8 + pix * 8 + (c & 7)] = val;
+    store1(reinterpret_cast<T*>(a.Z) + ((size_t)img * ZCB + (c >> 3)) * hw * 8 + pix * 8 + (c & 7),
+           val);
   }
 }
 
@@ -253,10 +262,14 @@ int grid_for(size_t total) {
 }  // namespace
 
 hipError_t launch_stage(const float* frames, int n, int h, int w, float* out, int hp, int wp,
-                        hipStream_t s) {
+                        int bf16act, hipStream_t s) {
   const size_t total = (size_t)n * hp * wp;
   if (!total) return hipSuccess;
-  stage_kernel<<<grid_for(total), 256, 0, s>>>(frames, n, h, w, out, hp, wp);
+  if (bf16act)
+    stage_kernel<bf16><<<grid_for(total), 256, 0, s>>>(frames, n, h, w, reinterpret_cast<bf16*>(out),
+                                                        hp, wp);
+  else
+    stage_kernel<float><<<grid_for(total), 256, 0, s>>>(frames, n, h, w, out, hp, wp);
   return hipGetLastError();
 }
 
@@ -298,10 +311,17 @@ hipError_t launch_warp_cost_volume(const CvArgs& a, hipStream_t s) {
   if (a.radius != 4 || a.C % 8 != 0 || a.zcb != (81 + 2 + 7) / 8) return hipErrorInvalidValue;
   if (a.splits < 1 || a.cps < 1 || (a.splits > 1 && !a.partial)) return hipErrorInvalidValue;
   dim3 grid(cdiv(a.w, CV_TX), cdiv(a.h, CV_TY), a.n * a.splits);
-  warp_cv_kernel<4><<<grid, 256, 0, s>>>(a);
+  if (a.bf16act)
+    warp_cv_kernel<4, bf16><<<grid, 256, 0, s>>>(a);
+  else
+    warp_cv_kernel<4, float><<<grid, 256, 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.splits == 1) return e;
-  cv_reduce_kernel<4><<<grid_for((size_t)a.n * a.zcb * 8 * a.h * a.w), 256, 0, s>>>(a);
+  const int g = grid_for((size_t)a.n * a.zcb * 8 * a.h * a.w);
+  if (a.bf16act)
+    cv_reduce_kernel<4, bf16><<<g, 256, 0, s>>>(a);
+  else
+    cv_reduce_kernel<4, float><<<g, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -26,6 +26,10 @@ struct View {
   int cb0;  // first block of the view
 };
 
+// BF16 conv: channel blocks of 8 per K chunk and MFMA steps per full chunk.
+constexpr int BF_CPC = 2;
+constexpr int BF_STEPS = (9 * BF_CPC + 3) / 4;
+
 // One 3x3 conv layer as the MFMA kernels consume it.  Weights are packed
 // [cin_pad / kc][9 taps][kc][np] (tap = 3 * p + q), zero for padded input or
 // output channels; np = cout rounded up to 16.  Bias has np entries.
@@ -34,8 +38,10 @@ struct ConvLayer {
   int cin_pad;     // multiple of kc
   int kc;          // input channels per K chunk (= block size of the input)
   int np;          // cout rounded up to 16
-  float* w;        // device, packed
+  float* w;        // device, packed (bfloat16 bits for bfloat16 conv layers)
   float* b;        // device, np floats
+  int bf16;        // weights packed for conv3x3_bf16_mfma:
+                   // [cdiv(cin_pad / 8, BF_CPC)][BF_STEPS][4][np][8] bfloat16
 };
 
 struct ConvArgs {
@@ -50,6 +56,7 @@ struct ConvArgs {
   const float* w;
   const float* b;
   int nchunks, cout, np;
+  int nblk;  // input channel blocks of 8 (bfloat16 path: a chunk holds 2 blocks)
   int lrelu;
   float slope;
   int n;  // images
@@ -58,6 +65,7 @@ struct ConvArgs {
   // a reduction pass then applies bias, LeakyReLU, `add` and the store.
   int splits, cps;
   float* partial;
+  int bf16act;  // input and (blocked) output activations stored as bfloat16
 };
 
 // Launch plan of one conv: rows per wave (tile = 4 * mr rows x 16 columns)
@@ -73,10 +81,10 @@ hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, int mr, hipStre
 hipError_t launch_head(const ConvArgs& a, hipStream_t s);
 
 
-// NCHW float frames (n x 3 x h x w) -> blocked B = 4 (n x 1 x hp x wp x 4),
-// bottom/right edge replicated, channel 3 zero.
+// NCHW float frames (n x 3 x h x w) -> one channel block per pixel, bottom /
+// right edge replicated: float32 blocks of 4 (RGB, 0) or bfloat16 blocks of 8.
 hipError_t launch_stage(const float* frames, int n, int h, int w, float* out, int hp, int wp,
-                        hipStream_t s);
+                        int bf16act, hipStream_t s);
 
 // U = 2 * up2(flow), both compact NHWC with 2 channels: (n, h, w) -> (n, 2h, 2w).
 hipError_t launch_up2x2(const float* flow, int n, int h, int w, float* U, hipStream_t s);
@@ -97,6 +105,7 @@ struct CvArgs {
   // pass adds the splits in order and writes Z.
   int splits, cps;
   float* partial;
+  int bf16act;  // features and Z stored as bfloat16
 };
 struct CvPlan {
   int splits, cps;
