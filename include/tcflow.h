@@ -136,6 +136,40 @@ TC_API int tc_consistency_step(const float* stylized, const float* prev_out, con
                                const float* flow_bw, float alpha, int n, int h, int w, float* out,
                                unsigned char* mask_or_null, void* stream);
 
+/* ---- the paper's full consistency step ------------------------------------ */
+
+/* Parameters of Eq. 1-8 (paper Sec. 3.1 and Sec. 4.2): k1, k2 = upper clamps
+ * of the previous / next local weights, a_ph = photometric sharpness of the
+ * weights' exponentials, lambda = scale of the smoothness weight w_c,
+ * eta, kappa = step sizes of the momentum iteration, iterations = its count.
+ * tc_paper_default_params fills the paper's final setting (k1 0.3, k2 0.5,
+ * a_ph 6500, lambda 2, eta 0.15, kappa 0.2, 150 iterations). */
+typedef struct {
+  float k1, k2, a_ph, lambda, eta, kappa;
+  int iterations;
+} tc_paper_params;
+
+TC_API void tc_paper_default_params(tc_paper_params* p);
+TC_API size_t tc_paper_workspace_bytes(int n, int h, int w);
+
+/* O_t of the paper's step.  Inputs n x 3 x h x w: I_{t-1}, I_t, I_{t+1},
+ * P_{t-1}, P_t, P_{t+1}, O_{t-1}; flows n x 2 x h x w: flow_t_prev = flow from
+ * frame t to t-1 and flow_t_next = from t to t+1, both on t's grid.  Per pixel
+ * (warps are bilinear with border clamping):
+ *   w_p = min(exp(-a_ph |I_t - warp(I_{t-1})|^2), k1), w_n likewise with k2 (Eq. 3)
+ *   L_t = (1 - w_p - w_n) P_t + w_p warp(P_{t-1}) + w_n warp(P_{t+1})       (Eq. 2)
+ *   A_t = w_p warp(O_{t-1}) + (1 - w_p) L_t                                  (Eq. 4, 5)
+ *   w_c = lambda exp(-a_ph |I_t - A^I_t|^2), A^I_t as L_t over I             (Eq. 6, 7)
+ * then `iterations` steps of O <- O - eta grad E(O) + kappa (O - O_old) with
+ * grad E(O) = -Lap(O - P_t) + w_c (O - A_t) (Eq. 1 discretised with forward
+ * differences and Neumann borders; Eq. 8), from O = O_old = A_t.  `out`
+ * (n x 3 x h x w) must not alias an input. */
+TC_API int tc_consistency_paper(const float* I_prev, const float* I, const float* I_next,
+                                const float* P_prev, const float* P, const float* P_next,
+                                const float* O_prev, const float* flow_t_prev,
+                                const float* flow_t_next, const tc_paper_params* params, int n,
+                                int h, int w, float* out, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- measurement probe -------------------------------------------------- */
 
 /* Stage ids: TC_STAGE(level, op) for the per-level ops, plus three
@@ -154,6 +188,7 @@ enum {
 #define TC_STAGE_INPUT 1        /* frame staging (pad + relayout)       */
 #define TC_STAGE_OUTPUT 2       /* final upsample + crop of the flow     */
 #define TC_STAGE_CONSISTENCY 3  /* fused consistency step               */
+#define TC_STAGE_PAPER 4        /* the paper's consistency step (all kernels) */
 
 /* Bracket every launch of `stage` with a pair of hipEvents on its stream,
  * for up to `max_launches` launches (process-wide; a measurement aid, not

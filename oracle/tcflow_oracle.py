@@ -349,3 +349,88 @@ def warping_error(Vt, Vt1, flow_t_t1, mask):
     d = np.abs(np.asarray(Vt, np.float64) - Vh).sum(axis=0)
     M = np.asarray(mask, np.float64)
     return float((M * d).sum() / M.sum())
+
+
+# --------------------------------------------------------------------------
+# the paper's full consistency step (Sec. 3.1, Eq. 1-8)
+
+PAPER_DEFAULTS = dict(k1=0.3, k2=0.5, a_ph=6.5e3, lam=2.0, eta=0.15, kappa=0.2, iters=150)
+
+
+def photometric_weight(I, Iw, a_ph):
+    """Eq. 3: exp(-a_ph |I - Iw|^2), the squared norm over the RGB channels."""
+    d = np.asarray(I, np.float64) - np.asarray(Iw, np.float64)
+    return np.exp(-a_ph * (d ** 2).sum(axis=0))
+
+
+def laplacian(X):
+    """5-point Laplacian with Neumann borders: sum over the in-image
+    4-neighbours of (neighbour - centre), per channel.  X: (C, H, W)."""
+    X = np.asarray(X, np.float64)
+    out = np.zeros_like(X)
+    out[:, :, :-1] += X[:, :, 1:] - X[:, :, :-1]
+    out[:, :, 1:] += X[:, :, :-1] - X[:, :, 1:]
+    out[:, :-1, :] += X[:, 1:, :] - X[:, :-1, :]
+    out[:, 1:, :] += X[:, :-1, :] - X[:, 1:, :]
+    return out
+
+
+def paper_reference(I_prev, I, I_next, P_prev, P, P_next, O_prev, f_tp, f_tn, prm):
+    """A_t and w_c of the paper's consistency step.
+
+    f_tp: flow from frame t to t-1 (on t's grid); f_tn: flow from t to t+1.
+    Gamma is the backward bilinear warp with border clamping.
+      w_p = min(exp(-a_ph |I_t - Gamma(I_{t-1})|^2), k1)      (Eq. 3 + clamp)
+      w_n = min(exp(-a_ph |I_t - Gamma(I_{t+1})|^2), k2)
+      L_t  = (1 - w_p - w_n) P_t + w_p Gamma(P_{t-1}) + w_n Gamma(P_{t+1})   (Eq. 2)
+      G_t  = Gamma(O_{t-1})                                     (Eq. 4)
+      A_t  = w_p G_t + (1 - w_p) L_t                            (Eq. 5)
+      A^I_t = (1 - w_p - w_n) I_t + w_p Gamma(I_{t-1}) + w_n Gamma(I_{t+1})  (Eq. 6)
+      w_c  = lambda exp(-a_ph |I_t - A^I_t|^2)                   (Eq. 7)
+    Returns (A_t, w_c, w_p, w_n).
+    """
+    f_tp = np.asarray(f_tp, np.float64)
+    f_tn = np.asarray(f_tn, np.float64)
+    Ip_w = warp_clamp(np.asarray(I_prev, np.float64), f_tp)
+    In_w = warp_clamp(np.asarray(I_next, np.float64), f_tn)
+    Pp_w = warp_clamp(np.asarray(P_prev, np.float64), f_tp)
+    Pn_w = warp_clamp(np.asarray(P_next, np.float64), f_tn)
+    G = warp_clamp(np.asarray(O_prev, np.float64), f_tp)
+    I = np.asarray(I, np.float64)
+    P = np.asarray(P, np.float64)
+    w_p = np.minimum(photometric_weight(I, Ip_w, prm["a_ph"]), prm["k1"])
+    w_n = np.minimum(photometric_weight(I, In_w, prm["a_ph"]), prm["k2"])
+    L = (1 - w_p - w_n)[None] * P + w_p[None] * Pp_w + w_n[None] * Pn_w
+    A = w_p[None] * G + (1 - w_p)[None] * L
+    AI = (1 - w_p - w_n)[None] * I + w_p[None] * Ip_w + w_n[None] * In_w
+    w_c = prm["lam"] * photometric_weight(I, AI, prm["a_ph"])
+    return A, w_c, w_p, w_n
+
+
+def energy_gradient(O, P, A, w_c):
+    """Gradient of the discrete Eq. 1, E = 1/2 sum |D(O - P)|^2 +
+    1/2 sum w_c |O - A|^2 with forward differences D:
+    -Laplacian(O - P) + w_c (O - A)."""
+    return -laplacian(np.asarray(O) - P) + w_c[None] * (np.asarray(O) - A)
+
+
+def poisson_solve(P, A, w_c, prm, O0=None):
+    """Eq. 8, gradient descent with momentum on Eq. 1:
+    O^{j+1} = O^j - eta grad E(O^j) + kappa (O^j - O^{j-1}),
+    O^0 = O^{-1} = A_t (or O0), for prm['iters'] iterations."""
+    P = np.asarray(P, np.float64)
+    A = np.asarray(A, np.float64)
+    O = np.array(A if O0 is None else O0, np.float64)
+    O_old = O.copy()
+    for _ in range(prm["iters"]):
+        O_new = O - prm["eta"] * energy_gradient(O, P, A, w_c) + prm["kappa"] * (O - O_old)
+        O_old, O = O, O_new
+    return O
+
+
+def paper_consistency(I_prev, I, I_next, P_prev, P, P_next, O_prev, f_tp, f_tn, prm=None):
+    """O_t of the paper's step: reference A_t and weight w_c (Eq. 2-7), then
+    the screened-Poisson solve (Eq. 1) by Eq. 8.  Returns (O_t, A_t, w_c)."""
+    prm = dict(PAPER_DEFAULTS, **(prm or {}))
+    A, w_c, _, _ = paper_reference(I_prev, I, I_next, P_prev, P, P_next, O_prev, f_tp, f_tn, prm)
+    return poisson_solve(P, A, w_c, prm), A, w_c

@@ -605,6 +605,60 @@ int tc_consistency_step(const float* stylized, const float* prev_out, const floa
   return e == hipSuccess ? TC_OK : TC_ERR_HIP;
 }
 
+void tc_paper_default_params(tc_paper_params* p) {
+  if (!p) return;
+  p->k1 = 0.3f;
+  p->k2 = 0.5f;
+  p->a_ph = 6.5e3f;
+  p->lambda = 2.0f;
+  p->eta = 0.15f;
+  p->kappa = 0.2f;
+  p->iterations = 150;
+}
+
+size_t tc_paper_workspace_bytes(int n, int h, int w) {
+  if (!shape_ok(n, h, w)) return 0;
+  return 16 * align_up((size_t)n * h * w * sizeof(float), kAlign);
+}
+
+int tc_consistency_paper(const float* I_prev, const float* I, const float* I_next,
+                         const float* P_prev, const float* P, const float* P_next,
+                         const float* O_prev, const float* flow_t_prev, const float* flow_t_next,
+                         const tc_paper_params* prm, int n, int h, int w, float* out, void* ws,
+                         size_t ws_bytes, void* stream) {
+  if (!I_prev || !I || !I_next || !P_prev || !P || !P_next || !O_prev || !flow_t_prev ||
+      !flow_t_next || !prm || !out || !ws || !shape_ok(n, h, w))
+    return TC_ERR_INVALID_ARG;
+  if (!(prm->k1 >= 0.f && prm->k2 >= 0.f && prm->k1 + prm->k2 <= 1.f && prm->a_ph >= 0.f &&
+        prm->lambda >= 0.f && prm->eta >= 0.f && prm->kappa >= 0.f) ||
+      prm->iterations < 0 || prm->iterations > 100000)
+    return TC_ERR_INVALID_ARG;
+  if (!aligned(ws) || ws_bytes < tc_paper_workspace_bytes(n, h, w)) return TC_ERR_WORKSPACE;
+  const float* ins[] = {I_prev, I, I_next, P_prev, P, P_next, O_prev, flow_t_prev, flow_t_next};
+  for (const float* q : ins)
+    if (q == out) return TC_ERR_INVALID_ARG;
+  const size_t pl = align_up((size_t)n * h * w * sizeof(float), kAlign);
+  char* base = static_cast<char*>(ws);
+  PaperArgs a;
+  a.I_prev = I_prev; a.I = I; a.I_next = I_next;
+  a.P_prev = P_prev; a.P = P; a.P_next = P_next;
+  a.O_prev = O_prev; a.f_tp = flow_t_prev; a.f_tn = flow_t_next;
+  a.k1 = prm->k1; a.k2 = prm->k2; a.a_ph = prm->a_ph; a.lambda = prm->lambda;
+  a.eta = prm->eta; a.kappa = prm->kappa; a.iters = prm->iterations;
+  a.n = n; a.h = h; a.w = w;
+  a.R = reinterpret_cast<float*>(base);
+  a.wc = reinterpret_cast<float*>(base + 3 * pl);
+  a.O0 = reinterpret_cast<float*>(base + 4 * pl);
+  a.O1 = reinterpret_cast<float*>(base + 7 * pl);
+  a.O2 = reinterpret_cast<float*>(base + 10 * pl);
+  a.O3 = reinterpret_cast<float*>(base + 13 * pl);
+  hipStream_t s = (hipStream_t)stream;
+  probe_begin(TC_STAGE_PAPER, s);
+  const hipError_t e = launch_paper_step(a, out, 6, s);
+  probe_end(TC_STAGE_PAPER, s);
+  return e == hipSuccess ? TC_OK : TC_ERR_HIP;
+}
+
 int tc_probe_enable(int stage, int max_launches) {
   if (max_launches <= 0 || max_launches > (1 << 20)) return TC_ERR_INVALID_ARG;
   tc_probe_disable();

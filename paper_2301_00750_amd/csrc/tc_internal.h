@@ -119,6 +119,18 @@ hipError_t launch_warp_cost_volume(const CvArgs& a, hipStream_t s);
 hipError_t launch_final_flow(const float* flow1, int n, int h1, int w1, float* out_a,
                              float* out_b, int nsplit, int H, int W, hipStream_t s);
 
+// The paper's consistency step (Eq. 1-8).  Frames NCHW (n x 3 x h x w),
+// flows n x 2 x h x w: f_tp = flow from t to t-1, f_tn = flow from t to t+1.
+// Workspace planes: R (3), wc (1), O0..O3 (3 each).
+struct PaperArgs {
+  const float *I_prev, *I, *I_next, *P_prev, *P, *P_next, *O_prev, *f_tp, *f_tn;
+  float k1, k2, a_ph, lambda, eta, kappa;
+  int iters;
+  int n, h, w;
+  float *R, *wc, *O0, *O1, *O2, *O3;
+};
+hipError_t launch_paper_step(const PaperArgs& a, float* out, int block_iters, hipStream_t s);
+
 hipError_t launch_consistency(const float* P, const float* Oprev, const float* ffw,
                               const float* fbw, float alpha, int n, int h, int w, float* out,
                               unsigned char* mask, hipStream_t s);

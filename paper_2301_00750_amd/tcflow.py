@@ -24,10 +24,11 @@ EXPORTS = (
     "tc_pyramid_bytes", "tc_pyramid", "tc_decoder_workspace_bytes", "tc_flow_from_pyramids",
     "tc_flow_workspace_bytes", "tc_flow_estimate", "tc_flow_estimate_pair",
     "tc_consistency_step", "tc_probe_enable", "tc_probe_read", "tc_probe_disable",
+    "tc_paper_default_params", "tc_paper_workspace_bytes", "tc_consistency_paper",
 )
 
 TC_OP_PYR_A, TC_OP_PYR_B, TC_OP_UP2, TC_OP_COST_VOLUME, TC_OP_C1, TC_OP_C2, TC_OP_C3, TC_OP_HEAD = range(8)
-TC_STAGE_INPUT, TC_STAGE_OUTPUT, TC_STAGE_CONSISTENCY = 1, 2, 3
+TC_STAGE_INPUT, TC_STAGE_OUTPUT, TC_STAGE_CONSISTENCY, TC_STAGE_PAPER = 1, 2, 3, 4
 
 
 def stage_id(level, op):
@@ -57,6 +58,13 @@ class NetDesc(ctypes.Structure):
         return s
 
 
+class PaperParams(ctypes.Structure):
+    """tc_paper_params: k1, k2, a_ph, lambda, eta, kappa, iterations."""
+    _fields_ = [("k1", ctypes.c_float), ("k2", ctypes.c_float), ("a_ph", ctypes.c_float),
+                ("lam", ctypes.c_float), ("eta", ctypes.c_float), ("kappa", ctypes.c_float),
+                ("iterations", ctypes.c_int)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
@@ -79,6 +87,10 @@ def _load():
         "tc_probe_enable": (ci, [ci, ci]),
         "tc_probe_read": (ci, [ctypes.POINTER(ci), ctypes.POINTER(cf)]),
         "tc_probe_disable": (None, []),
+        "tc_paper_default_params": (None, [ctypes.POINTER(PaperParams)]),
+        "tc_paper_workspace_bytes": (sz, [ci, ci, ci]),
+        "tc_consistency_paper": (ci, [vp] * 9 + [ctypes.POINTER(PaperParams), ci, ci, ci, vp, vp,
+                                                 sz, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -227,6 +239,39 @@ def consistency_step(stylized, prev_out, flow_fw, flow_bw, alpha, out=None, mask
         _ptr(stylized), _ptr(prev_out), _ptr(flow_fw), _ptr(flow_bw), float(alpha), n, h, w,
         _ptr(o), _ptr(m), _stream(stream)))
     return (o, m) if mask else o
+
+
+def paper_params(**kw):
+    """The paper's final parameter set, with keyword overrides
+    (k1, k2, a_ph, lam, eta, kappa, iterations)."""
+    p = PaperParams()
+    _lib.tc_paper_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def consistency_paper(I_prev, I, I_next, P_prev, P, P_next, O_prev, flow_t_prev, flow_t_next,
+                      params=None, out=None, ws=None, stream=None):
+    """O_t of the paper's full consistency step (tc_consistency_paper)."""
+    for name, t in (("I_prev", I_prev), ("I", I), ("I_next", I_next), ("P_prev", P_prev),
+                    ("P", P), ("P_next", P_next), ("O_prev", O_prev)):
+        _frames(t, name, 3)
+    _frames(flow_t_prev, "flow_t_prev", 2)
+    _frames(flow_t_next, "flow_t_next", 2)
+    n, _, h, w = I.shape
+    for t in (I_prev, I_next, P_prev, P, P_next, O_prev, flow_t_prev, flow_t_next):
+        if t.shape[0] != n or t.shape[2:] != I.shape[2:]:
+            raise ValueError("consistency_paper: shapes differ")
+    prm = params if params is not None else paper_params()
+    if ws is None:
+        ws = _workspace(_lib.tc_paper_workspace_bytes(n, h, w), I.device)
+    o = out if out is not None else torch.empty_like(I)
+    _check("tc_consistency_paper", _lib.tc_consistency_paper(
+        _ptr(I_prev), _ptr(I), _ptr(I_next), _ptr(P_prev), _ptr(P), _ptr(P_next), _ptr(O_prev),
+        _ptr(flow_t_prev), _ptr(flow_t_next), ctypes.byref(prm), n, h, w, _ptr(o), _ptr(ws),
+        ws.numel() * ws.element_size(), _stream(stream)))
+    return o
 
 
 class Probe:

@@ -343,3 +343,62 @@ def test_bf16_fullhd_pair_vs_oracle(tc):
         mean, mx = flow_err(a, b)
         say(f"   {name}: EPE mean={mean:.3e} max={mx:.3e}")
         assert mean <= 0.25
+
+
+# ---------------------------------------------------------------- the paper's consistency step
+#
+# Tolerance: the weights are exp(-a_ph d) with a_ph = 6500, so a float32
+# rounding of d (~1e-7) moves a weight by up to 6500 * 1e-7 of itself; the
+# output then differs by at most ~1e-3 of the spread of the blended values.
+# The momentum iteration is contractive at these step sizes, so the solve
+# does not amplify it.  Measured differences are ~5e-7; bar: 1e-4 on values
+# in [0, 1] (well inside the bound, so a real error fails it).
+
+
+def paper_inputs(h, w, seed, flows="gt"):
+    sc = synth.LayeredScene(w, h, seed=seed, max_shift=4.0)
+    I = [sc.frame(t) for t in range(3)]
+    P = [synth.stylize(x, t) for t, x in enumerate(I)]
+    O_prev = synth.stylize(I[0], 7)
+    if flows == "gt":
+        f_tp, _ = sc.gt_flow(1, 0)
+        f_tn, _ = sc.gt_flow(1, 2)
+    else:
+        gen = torch.Generator().manual_seed(seed)
+        f_tp = 3 * torch.randn(2, h, w, generator=gen)
+        f_tn = 3 * torch.randn(2, h, w, generator=gen)
+    return I, P, O_prev, f_tp, f_tn
+
+
+@pytest.mark.parametrize("hw,iters,flows", [((96, 128), 0, "gt"), ((96, 128), 1, "gt"),
+                                            ((77, 131), 7, "random"), ((96, 128), 150, "gt"),
+                                            ((200, 333), 150, "gt")])
+def test_paper_consistency_vs_oracle(tc, hw, iters, flows):
+    h, w = hw
+    I, P, Op, f_tp, f_tn = paper_inputs(h, w, 5, flows)
+    say(f"[paper step] {h}x{w} iterations={iters} flows={flows}")
+    prm = tc.paper_params(iterations=iters)
+    out = tc.consistency_paper(g(I[0][None]), g(I[1][None]), g(I[2][None]), g(P[0][None]),
+                               g(P[1][None]), g(P[2][None]), g(Op[None]), g(f_tp[None]),
+                               g(f_tn[None]), prm)
+    torch.cuda.synchronize()
+    ref, A, w_c = O.paper_consistency(f64(I[0]), f64(I[1]), f64(I[2]), f64(P[0]), f64(P[1]),
+                                      f64(P[2]), f64(Op), f64(f_tp), f64(f_tn),
+                                      dict(iters=iters))
+    err = np.abs(f64(out[0]) - ref).max()
+    say(f"   max |GPU - oracle| = {err:.2e}, mean w_c = {w_c.mean():.3f}, "
+        f"|O - A| mean = {np.abs(ref - A).mean():.3e}")
+    assert err <= 1e-4
+
+
+def test_paper_consistency_fixed_point_and_zero_clamps(tc):
+    h, w = 64, 80
+    I, P, Op, f_tp, f_tn = paper_inputs(h, w, 9)
+    args = [g(I[0][None]), g(I[1][None]), g(I[2][None]), g(P[0][None]), g(P[1][None]),
+            g(P[2][None]), g(Op[None]), g(f_tp[None]), g(f_tn[None])]
+    out = tc.consistency_paper(*args, params=tc.paper_params(k1=0.0, k2=0.0))
+    torch.cuda.synchronize()
+    # k1 = k2 = 0: A = P, hence R = w_c P - Lap P and O stays P up to rounding
+    assert torch.allclose(out, args[4], atol=1e-5, rtol=0)
+    with pytest.raises(tc.TcError):
+        tc.consistency_paper(*args, params=tc.paper_params(k1=0.7, k2=0.5))
