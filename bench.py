@@ -11,7 +11,9 @@ seeded affine motion (played forward then backward), a seeded colour-map
 "stylizer", alpha swept over {0, .25, .5, .75, 1}; all frames resident in HBM
 before timing starts.  The headline is the FP32 path; the BF16 form (BF16
 activations and weights on MFMA with FP32 accumulation; flows, upsampling and
-warp coordinates in FP32) is measured after it with its EPE and speedup.
+warp coordinates in FP32) and the FP8 form (FP8 E4M3 operands for the
+estimators of the two finest levels, BF16 elsewhere) are measured after it
+with their EPE and speedup.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -34,6 +36,7 @@ from paper_2301_00750_amd import synth  # noqa: E402
 
 PEAK_FP32_MFMA = 157.3  # TFLOP/s, MI355X dense FP32 matrix
 PEAK_BF16_MFMA = 2500.0  # TFLOP/s, MI355X dense BF16 matrix
+PEAK_FP8_MFMA = 5000.0  # TFLOP/s, MI355X dense FP8 matrix
 PEAK_HBM = 8000.0  # GB/s
 ALPHAS = (0.0, 0.25, 0.5, 0.75, 1.0)
 METRIC = "1080p frames/s (flow+consistency) at stated EPE vs FP64 oracle; p99 frame ms"
@@ -159,7 +162,7 @@ def main():
     ap.add_argument("--frames", type=int, default=60)
     ap.add_argument("--cpu-frames", type=int, default=2,
                     help="frames of the workload the FP64 oracle is timed on (0 = skip)")
-    ap.add_argument("--forms", default="bf16",
+    ap.add_argument("--forms", default="bf16,fp8",
                     help="comma-separated precision forms measured after the FP32 path ('' = none)")
     ap.add_argument("--paper-steps", type=int, default=30,
                     help="1080p frames of the paper's full consistency step to time (0 = skip)")
@@ -252,12 +255,12 @@ def main():
     forms = {}
     nets = {"fp32": r["net"]}
     for form in [f for f in args.forms.split(",") if f]:
-        prec = {"bf16": tcflow.TC_BF16}[form]
+        prec = {"bf16": tcflow.TC_BF16, "fp8": tcflow.TC_FP8_E4M3}[form]
         log(f"{form}: timing {K} steps")
         rf = measure(tcflow, desc, blob, prec, I, P, K, args.warmup, args.frames)
         log(f"{form}: {rf['fps']:.1f} frames/s, {rf['ms']:.3f} ms/frame")
         nets[form] = rf["net"]
-        peak = PEAK_BF16_MFMA
+        peak = PEAK_BF16_MFMA if form == "bf16" else PEAK_FP8_MFMA
         ach = c1_flops(desc, H, W) / (rf["c1_alone_ms"] * 1e-3) / 1e12
         forms[form] = {
             "value": round(rf["fps"], 2), "unit": "frames/s", "ms_per_step": round(rf["ms"], 4),

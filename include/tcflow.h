@@ -61,6 +61,11 @@ typedef struct tc_net tc_net; /* opaque */
 TC_API const char* tc_status_str(int status);
 TC_API const char* tc_version(void);
 
+/* Host-side float -> FP8 E4M3 encoder used for the FP8 weights (OCP 8-bit
+ * floating point "E4M3FN": bias 7, no infinities, largest finite 448; round
+ * to nearest even, saturating).  Plain host memory, n values. */
+TC_API void tc_fp8_e4m3_encode(const float* in, unsigned char* out, size_t n);
+
 /* Number of float32 values of the weight blob for `desc`.  Blob layout,
  * layer after layer: W[cout][cin][3][3] then b[cout]; order: pyramid convs
  * of level 1..L (stride 2: C_{l-1} -> C_l with C_0 = 3, then stride 1:
@@ -69,7 +74,12 @@ TC_API const char* tc_version(void);
 TC_API size_t tc_weight_floats(const tc_net_desc* desc);
 
 /* Copies the host weight blob to the current HIP device, packed for the
- * kernels of `precision`.  Paper, Sec. 3.2: PWC-Net-shaped network with
+ * kernels of `precision`: TC_FP32 (FP32 activations, FP32 MFMA); TC_BF16
+ * (BF16 activations and weights, FP32 accumulation); TC_FP8_E4M3 (BF16
+ * activations rounded to FP8 with a per-image, per-tensor scale max|x| / 448
+ * when a conv stages them, FP8 weights with per-output-channel scales, FP32
+ * accumulation).  In every form the flows, their upsampling and accumulation
+ * and the warp coordinates are FP32, and the cost volume accumulates in FP32.  Paper, Sec. 3.2: PWC-Net-shaped network with
  * light estimators (a conv feature pyramid, warping, correlation and a CNN
  * flow estimator per level).  *out is set only on TC_OK. */
 TC_API int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_floats,

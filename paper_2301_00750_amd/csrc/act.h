@@ -51,3 +51,36 @@ __device__ inline void store1(float* p, float v) { *p = v; }
 __device__ inline void store1(bf16* p, float v) { *p = f2bf(v); }
 
 }  // namespace tc
+
+namespace tc {
+
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+
+// Largest finite value of FP8 E4M3 (OCP "fn" variant used by gfx950).
+constexpr float kFp8Max = 448.f;
+
+// 8 floats -> 8 FP8 E4M3 (round to nearest even, saturated to +-448), after
+// multiplying by `inv_scale`.
+__device__ inline u2v pack8_fp8(const float (&v)[8], float inv_scale) {
+  float s[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s[i] = fminf(fmaxf(v[i] * inv_scale, -kFp8Max), kFp8Max);
+  int lo = __builtin_amdgcn_cvt_pk_fp8_f32(s[0], s[1], 0, false);
+  lo = __builtin_amdgcn_cvt_pk_fp8_f32(s[2], s[3], lo, true);
+  int hi = __builtin_amdgcn_cvt_pk_fp8_f32(s[4], s[5], 0, false);
+  hi = __builtin_amdgcn_cvt_pk_fp8_f32(s[6], s[7], hi, true);
+  return u2v{(unsigned)lo, (unsigned)hi};
+}
+
+// Wave-wide maximum folded into a per-image slot (values are >= 0, so their
+// float bit patterns order like unsigned integers).  Maximum is independent
+// of the order in which waves arrive.
+__device__ inline void record_amax(unsigned* slot, float v) {
+  if (!slot) return;
+  v = fabsf(v);
+  if (!(v <= 3.0e38f)) v = 3.0e38f;  // NaN / inf saturate
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(slot, __float_as_uint(v));
+}
+
+}  // namespace tc

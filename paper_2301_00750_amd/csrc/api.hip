@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <cmath>
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -16,6 +17,7 @@ struct tc_net {
   tc_net_desc d;
   int precision;
   int bf16act;      // activations stored as bfloat16, convs on BF16 MFMA
+  int fp8;          // convs on FP8 E4M3 MFMA (activations still stored as bfloat16)
   int esz;          // bytes per stored activation element
   int ncv;          // (2r+1)^2
   int zcb;          // blocks of the cost-volume buffer (ncv + 2, rounded up to 8)
@@ -92,12 +94,20 @@ bool shape_ok(int n, int h, int w) {
 // frame (B = 4) and the scratch for each level's first conv.
 struct PyrLayout {
   size_t off[9];
-  size_t stage, tmp, partial, total;
+  size_t stage, tmp, partial, slots, total;
 };
 
+// amax slots (n unsigned each): stage, then per level tmp and features
+inline size_t pyr_slot(int n, int which) { return (size_t)which * n; }
+inline int pyr_slot_stage() { return 0; }
+inline int pyr_slot_tmp(int l) { return 1 + 2 * (l - 1); }
+inline int pyr_slot_feat(int l) { return 2 + 2 * (l - 1); }
+
 int layer_chunks(const ConvLayer& L) {
-  return L.bf16 ? cdiv(L.cin_pad / 8, BF_CPC) : L.cin_pad / L.kc;
+  return (L.bf16 || L.fp8) ? cdiv(L.cin_pad / 8, BF_CPC) : L.cin_pad / L.kc;
 }
+
+AmaxIn amax_plain(const unsigned* p) { return AmaxIn{p, p, 1 << 30}; }
 
 size_t layer_partial_bytes(const ConvLayer& L, int out_h, int out_w, int n, int stride) {
   const ConvPlan p = plan_conv(out_h, out_w, n, layer_chunks(L), stride, L.np);
@@ -126,14 +136,18 @@ PyrLayout pyr_layout(const tc_net* net, int n, int h, int w) {
   pos = align_up(pos + tmp, kAlign);
   p.partial = pos;
   pos = align_up(pos + part, kAlign);
+  p.slots = pos;
+  pos = align_up(pos + (size_t)(1 + 2 * d.levels) * n * sizeof(unsigned), kAlign);
   p.total = pos;
   return p;
 }
 
 // ---- decoder scratch for a batch of nb images (n pairs -> nb = 2n)
 struct DecLayout {
-  size_t flow[2], U, Z, H1, H23, partial, total;
+  size_t flow[2], U, Z, H1, H23, partial, slots, total;
 };
+// decoder amax slots (nb unsigned each): per level Z, H1, H2
+inline int dec_slot(int l, int which) { return 3 * (l - 1) + which; }
 
 DecLayout dec_layout(const tc_net* net, int nb, int h, int w) {
   DecLayout L;
@@ -163,6 +177,7 @@ DecLayout dec_layout(const tc_net* net, int nb, int h, int w) {
     if (pb > part) part = pb;
   }
   L.partial = take(part);
+  L.slots = take((size_t)3 * net->d.levels * nb * sizeof(unsigned));
   L.total = pos;
   return L;
 }
@@ -220,6 +235,63 @@ void pack_conv_bf16(const float* W, const float* b, int cout, int cin, int cin_p
   for (int o = 0; o < cout; ++o) bout[o] = b[o];
 }
 
+// float -> FP8 E4M3 as defined by the OCP 8-bit floating point specification
+// ("E4M3FN": 1 sign, 4 exponent bits with bias 7, 3 mantissa bits, no
+// infinities, largest finite 448, subnormals m/8 * 2^-6): round to nearest
+// even, saturate to +-448, NaN -> 0x7f.
+uint8_t host_f2e4m3(float f) {
+  if (std::isnan(f)) return 0x7f;
+  const uint8_t sign = std::signbit(f) ? 0x80 : 0x00;
+  const float a = std::fabs(f);
+  if (a >= 448.f) return sign | 0x7e;
+  int e2 = 0;
+  std::frexp(a, &e2);  // a = m 2^e2, m in [0.5, 1)
+  int E = e2 - 1;      // a = 1.xxx 2^E
+  if (a == 0.f) return sign;
+  if (E < -6) {        // subnormal: units of 2^-9
+    const int q = (int)std::nearbyint(std::ldexp(a, 9));
+    return sign | (uint8_t)q;  // q == 8 is the smallest normal, encoded 0x08
+  }
+  int q = (int)std::nearbyint(std::ldexp(a, 3 - E));  // in [8, 16]
+  if (q == 16) {
+    q = 8;
+    ++E;
+  }
+  if (E + 7 > 15 || (E + 7 == 15 && q - 8 == 7)) return sign | 0x7e;
+  return sign | (uint8_t)(((E + 7) << 3) | (q - 8));
+}
+
+// FP8 packing: the order of pack_conv_bf16, one byte per value, each output
+// channel scaled by scale[o] = max|W[o]| / 448.
+void pack_conv_fp8(const float* W, const float* b, int cout, int cin, int cin_pad,
+                   const std::vector<int>& cmap, std::vector<uint8_t>& wout,
+                   std::vector<float>& bout, std::vector<float>& scale, int& np) {
+  np = (cout + 15) / 16 * 16;
+  const int nblk = cin_pad / 8, nch = cdiv(nblk, BF_CPC);
+  wout.assign((size_t)nch * BF_STEPS * 4 * np * 8, 0);
+  bout.assign(np, 0.f);
+  scale.assign(np, 1.f);
+  for (int o = 0; o < cout; ++o) {
+    float m = 0.f;
+    for (int c = 0; c < cin * 9; ++c) m = std::max(m, std::fabs(W[(size_t)o * cin * 9 + c]));
+    scale[o] = m > 0.f ? m / 448.f : 1.f;
+  }
+  for (int c = 0; c < nch; ++c) {
+    const int cpc = std::min(BF_CPC, nblk - c * BF_CPC);
+    for (int kb = 0; kb < 9 * cpc; ++kb) {
+      const int tap = kb / cpc, cbi = kb % cpc, st = kb / 4, g = kb % 4;
+      for (int o = 0; o < cout; ++o)
+        for (int j = 0; j < 8; ++j) {
+          const int src = cmap[(c * BF_CPC + cbi) * 8 + j];
+          if (src < 0) continue;
+          wout[((((size_t)c * BF_STEPS + st) * 4 + g) * np + o) * 8 + j] =
+              host_f2e4m3(W[((size_t)o * cin + src) * 9 + tap] / scale[o]);
+        }
+    }
+  }
+  for (int o = 0; o < cout; ++o) bout[o] = b[o];
+}
+
 View plain_view(const float* p, int cbt, int cb0 = 0) {
   View v;
   v.a = p;
@@ -233,7 +305,7 @@ View plain_view(const float* p, int cbt, int cb0 = 0) {
 int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, int in_h, int in_w,
                float* out, int out_cbt, int out_cb0, int compact, const float* add, int out_h,
                int out_w, int relu, float slope, int n, int stride, int stage, float* partial,
-               int act_bf16, hipStream_t s) {
+               int act_bf16, const AmaxIn* ain, unsigned* aout, hipStream_t s) {
   ConvArgs a;
   a.in0 = in0;
   a.in1 = in1;
@@ -251,7 +323,11 @@ int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, in
   a.b = L.b;
   a.nchunks = layer_chunks(L);
   a.nblk = L.cin_pad / 8;
-  a.bf16act = L.bf16 ? 1 : 0;
+  a.bf16act = (L.bf16 || L.fp8) ? 1 : 0;
+  a.fp8 = L.fp8;
+  a.wscale = L.ws;
+  for (int i = 0; i < 3; ++i) a.ain[i] = ain ? ain[i] : AmaxIn{nullptr, nullptr, 0};
+  a.aout = aout;
   a.cout = L.cout;
   a.np = L.np;
   a.lrelu = relu;
@@ -284,8 +360,12 @@ int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, cha
   float* stage = reinterpret_cast<float*>(pyr + p.stage);
   float* tmp = reinterpret_cast<float*>(pyr + p.tmp);
   float* part = reinterpret_cast<float*>(pyr + p.partial);
+  unsigned* slots = net->fp8 ? reinterpret_cast<unsigned*>(pyr + p.slots) : nullptr;
+  auto slot = [&](int which) { return slots ? slots + pyr_slot(n, which) : nullptr; };
+  if (slots) TC_TRY_HIP(launch_zero_u32(slots, (size_t)(1 + 2 * d.levels) * n, s));
   probe_begin(TC_STAGE_INPUT, s);
-  TC_TRY_HIP(launch_stage(frames, n, h, w, stage, g.hp, g.wp, net->bf16act, s));
+  TC_TRY_HIP(launch_stage(frames, n, h, w, stage, g.hp, g.wp, net->bf16act, slot(pyr_slot_stage()),
+                          s));
   probe_end(TC_STAGE_INPUT, s);
   const float* in = stage;
   int in_cbt = 1, in_h = g.hp, in_w = g.wp;
@@ -293,13 +373,19 @@ int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, cha
     const int C = d.ch[l - 1];
     float* feat = reinterpret_cast<float*>(pyr + p.off[l]);
     const ConvLayer& La = net->pyr[l - 1][0];
-    int st = conv_layer(La, plain_view(in, in_cbt), La.cin_pad / (La.bf16 ? 8 : La.kc),
+    const AmaxIn ain_a[3] = {amax_plain(slot(l == 1 ? pyr_slot_stage() : pyr_slot_feat(l - 1))),
+                             {nullptr, nullptr, 0}, {nullptr, nullptr, 0}};
+    const AmaxIn ain_b[3] = {amax_plain(slot(pyr_slot_tmp(l))), {nullptr, nullptr, 0},
+                             {nullptr, nullptr, 0}};
+    int st = conv_layer(La, plain_view(in, in_cbt), La.cin_pad / ((La.bf16 || La.fp8) ? 8 : La.kc),
                         plain_view(in, in_cbt), in_h, in_w, tmp, C / 8, 0, 0, nullptr, g.h[l], g.w[l],
-                        1, d.leaky, n, 2, TC_STAGE(l, TC_OP_PYR_A), part, net->bf16act, s);
+                        1, d.leaky, n, 2, TC_STAGE(l, TC_OP_PYR_A), part, net->bf16act, ain_a,
+                        slot(pyr_slot_tmp(l)), s);
     if (st) return st;
     st = conv_layer(net->pyr[l - 1][1], plain_view(tmp, C / 8), C / 8, plain_view(tmp, C / 8),
                     g.h[l], g.w[l], feat, C / 8, 0, 0, nullptr, g.h[l], g.w[l], 1, d.leaky, n, 1,
-                    TC_STAGE(l, TC_OP_PYR_B), part, net->bf16act, s);
+                    TC_STAGE(l, TC_OP_PYR_B), part, net->bf16act, ain_b, slot(pyr_slot_feat(l)),
+                    s);
     if (st) return st;
     in = feat;
     in_cbt = C / 8;
@@ -323,6 +409,16 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
   float* H1 = reinterpret_cast<float*>(ws + D.H1);
   float* H23 = reinterpret_cast<float*>(ws + D.H23);
   float* part = reinterpret_cast<float*>(ws + D.partial);
+  unsigned* dslots = net->fp8 ? reinterpret_cast<unsigned*>(ws + D.slots) : nullptr;
+  auto dslot = [&](int l, int which) {
+    return dslots ? dslots + (size_t)dec_slot(l, which) * nb : nullptr;
+  };
+  const unsigned* pslots1 =
+      net->fp8 ? reinterpret_cast<const unsigned*>(pyr1 + p.slots) : nullptr;
+  const unsigned* pslots2 =
+      net->fp8 ? reinterpret_cast<const unsigned*>(pyr2 + p.slots) : nullptr;
+  if (dslots) TC_TRY_HIP(launch_zero_u32(dslots, (size_t)3 * d.levels * nb, s));
+  const AmaxIn none{nullptr, nullptr, 0};
   const int d0b = d.dec[0] / 8, d1b = d.dec[1] / 8, d23b = (d.dec[1] + d.dec[2]) / 8;
   int cur = 0;
   for (int l = d.levels; l >= 1; --l) {
@@ -356,22 +452,33 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
     cv.cps = cp.cps;
     cv.partial = part;
     cv.bf16act = net->bf16act;
+    cv.aout = dslot(l, 0);
     probe_begin(TC_STAGE(l, TC_OP_COST_VOLUME), s);
     TC_TRY_HIP(launch_warp_cost_volume(cv, s));
     probe_end(TC_STAGE(l, TC_OP_COST_VOLUME), s);
     const ConvLayer* L = net->dec[l - 1];
+    // F1 of images [0, n) is pyr1's level l, of [n, 2n) pyr2's
+    const AmaxIn fa{pslots1 ? pslots1 + pyr_slot(n, pyr_slot_feat(l)) : nullptr,
+                    pslots2 ? pslots2 + pyr_slot(n, pyr_slot_feat(l)) : nullptr, n};
+    const AmaxIn ain_c1[3] = {fa, amax_plain(dslot(l, 0)), none};
+    const AmaxIn ain_c2[3] = {amax_plain(dslot(l, 1)), none, none};
+    const AmaxIn ain_c3[3] = {amax_plain(dslot(l, 2)), none, none};
     int st = conv_layer(L[0], f1, C / 8, plain_view(Z, net->zcb), hl, wl, H1, d0b, 0, 0, nullptr,
-                        hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C1), part, net->bf16act, s);
+                        hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C1), part, net->bf16act,
+                        ain_c1, dslot(l, 1), s);
     if (st) return st;
     st = conv_layer(L[1], plain_view(H1, d0b), d0b, plain_view(H1, d0b), hl, wl, H23, d23b, 0, 0,
-                    nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C2), part, net->bf16act, s);
+                    nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C2), part, net->bf16act,
+                    ain_c2, dslot(l, 2), s);
     if (st) return st;
     st = conv_layer(L[2], plain_view(H23, d23b), d1b, plain_view(H23, d23b), hl, wl, H23, d23b,
-                    d1b, 0, nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C3), part, net->bf16act, s);
+                    d1b, 0, nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C3), part, net->bf16act,
+                    ain_c3, nullptr, s);
     if (st) return st;
     const int nxt = cur ^ 1;
     st = conv_layer(L[3], plain_view(H23, d23b), d23b, plain_view(H23, d23b), hl, wl, flows[nxt],
-                    0, 0, 1, Ul, hl, wl, 0, 0.f, nb, 1, TC_STAGE(l, TC_OP_HEAD), part, net->bf16act, s);
+                    0, 0, 1, Ul, hl, wl, 0, 0.f, nb, 1, TC_STAGE(l, TC_OP_HEAD), part, net->bf16act,
+                    nullptr, nullptr, s);
     if (st) return st;
     cur = nxt;
   }
@@ -399,7 +506,12 @@ const char* tc_status_str(int st) {
   }
 }
 
-const char* tc_version(void) { return "tcflow 0.2 (gfx950; FP32 and BF16 MFMA)"; }
+const char* tc_version(void) { return "tcflow 0.3 (gfx950; FP32, BF16 and FP8 E4M3 MFMA)"; }
+
+void tc_fp8_e4m3_encode(const float* in, unsigned char* out, size_t n) {
+  if (!in || !out) return;
+  for (size_t i = 0; i < n; ++i) out[i] = host_f2e4m3(in[i]);
+}
 
 size_t tc_weight_floats(const tc_net_desc* d) {
   if (!desc_ok(d)) return 0;
@@ -420,13 +532,15 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
                   int precision, tc_net** out) {
   if (!desc || !host_weights || !out) return TC_ERR_INVALID_ARG;
   if (!desc_ok(desc)) return TC_ERR_SHAPE;
-  if (precision != TC_FP32 && precision != TC_BF16) return TC_ERR_UNSUPPORTED;
+  if (precision != TC_FP32 && precision != TC_BF16 && precision != TC_FP8_E4M3)
+    return TC_ERR_UNSUPPORTED;
   if (n_floats != tc_weight_floats(desc)) return TC_ERR_SHAPE;
   tc_net* net = new (std::nothrow) tc_net();
   if (!net) return TC_ERR_HIP;
   net->d = *desc;
   net->precision = precision;
-  net->bf16act = precision == TC_BF16;
+  net->bf16act = precision == TC_BF16 || precision == TC_FP8_E4M3;
+  net->fp8 = precision == TC_FP8_E4M3;
   net->esz = net->bf16act ? 2 : 4;
   net->ncv = (2 * desc->radius + 1) * (2 * desc->radius + 1);
   net->zcb = (net->ncv + 2 + 7) / 8;
@@ -436,19 +550,31 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
   struct Packed {
     std::vector<char> w;
     std::vector<float> b;
+    std::vector<float> sc;  // FP8 per-output-channel weight scales
   };
   std::vector<Packed> packed;
   std::vector<ConvLayer*> slots;
   const float* src = host_weights;
+  // FP8 form: FP8 for the estimator convs of the two finest levels (most of
+  // the FLOPs); the pyramid, whose features feed every cost volume, and the
+  // coarse levels, whose errors are amplified by every upsampling on the way
+  // to full resolution, stay BF16.
   auto add_layer = [&](ConvLayer& cl, int cout, int cin, int kc, int cin_pad,
-                       const std::vector<int>& cmap, bool head) {
+                       const std::vector<int>& cmap, bool head, bool fp8_ok) {
     const float* W = src;
     const float* b = src + (size_t)cout * cin * 9;
     src += conv_floats(cout, cin);
     Packed pk;
     int np = 0;
-    cl.bf16 = net->bf16act && !head;
-    if (cl.bf16) {
+    cl.fp8 = net->fp8 && !head && fp8_ok;
+    cl.bf16 = net->bf16act && !head && !cl.fp8;
+    cl.ws = nullptr;
+    if (cl.fp8) {
+      std::vector<uint8_t> wq;
+      pack_conv_fp8(W, b, cout, cin, cin_pad, cmap, wq, pk.b, pk.sc, np);
+      pk.w.resize(wq.size());
+      memcpy(pk.w.data(), wq.data(), pk.w.size());
+    } else if (cl.bf16) {
       std::vector<uint16_t> wb;
       pack_conv_bf16(W, b, cout, cin, cin_pad, cmap, wb, pk.b, np);
       pk.w.resize(wb.size() * 2);
@@ -478,8 +604,8 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     // the staged frame is one block of 4 (float) or 8 (bfloat16) channels
     const int kc = (l == 1 && !net->bf16act) ? 4 : 8;
     const int pad = l == 1 ? kc : cin;
-    add_layer(net->pyr[l - 1][0], C, cin, kc, pad, identity(cin, pad), false);
-    add_layer(net->pyr[l - 1][1], C, C, 8, C, identity(C, C), false);
+    add_layer(net->pyr[l - 1][0], C, cin, kc, pad, identity(cin, pad), false, false);
+    add_layer(net->pyr[l - 1][1], C, C, 8, C, identity(C, C), false, false);
   }
   const int d0 = desc->dec[0], d1 = desc->dec[1], d2 = desc->dec[2];
   for (int l = 1; l <= L; ++l) {
@@ -492,10 +618,11 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     for (int k = 0; k < net->ncv; ++k) m[C + k] = k;
     m[C + net->ncv] = net->ncv + C;
     m[C + net->ncv + 1] = net->ncv + C + 1;
-    add_layer(net->dec[l - 1][0], d0, net->ncv + C + 2, 8, pad, m, false);
-    add_layer(net->dec[l - 1][1], d1, d0, 8, d0, identity(d0, d0), false);
-    add_layer(net->dec[l - 1][2], d2, d1, 8, d1, identity(d1, d1), false);
-    add_layer(net->dec[l - 1][3], 2, d1 + d2, 8, d1 + d2, identity(d1 + d2, d1 + d2), true);
+    const bool f8 = l <= 2;
+    add_layer(net->dec[l - 1][0], d0, net->ncv + C + 2, 8, pad, m, false, f8);
+    add_layer(net->dec[l - 1][1], d1, d0, 8, d0, identity(d0, d0), false, f8);
+    add_layer(net->dec[l - 1][2], d2, d1, 8, d1, identity(d1, d1), false, f8);
+    add_layer(net->dec[l - 1][3], 2, d1 + d2, 8, d1 + d2, identity(d1 + d2, d1 + d2), true, false);
   }
 
   // one device allocation for every layer
@@ -505,7 +632,7 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     offs.push_back(total);
     total = align_up(total + pk.w.size(), kAlign);
     offs.push_back(total);
-    total = align_up(total + pk.b.size() * sizeof(float), kAlign);
+    total = align_up(total + (pk.b.size() + pk.sc.size()) * sizeof(float), kAlign);
   }
   if (hipMalloc(&net->dmem, total) != hipSuccess) {
     delete net;
@@ -515,8 +642,12 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
   for (size_t i = 0; i < packed.size(); ++i) {
     memcpy(host.data() + offs[2 * i], packed[i].w.data(), packed[i].w.size());
     memcpy(host.data() + offs[2 * i + 1], packed[i].b.data(), packed[i].b.size() * sizeof(float));
+    if (!packed[i].sc.empty())
+      memcpy(host.data() + offs[2 * i + 1] + packed[i].b.size() * sizeof(float),
+             packed[i].sc.data(), packed[i].sc.size() * sizeof(float));
     slots[i]->w = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[2 * i]);
     slots[i]->b = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[2 * i + 1]);
+    if (slots[i]->fp8) slots[i]->ws = slots[i]->b + packed[i].b.size();
   }
   if (hipMemcpy(net->dmem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(net->dmem);

@@ -16,6 +16,8 @@
 //   A (16 x 4):  A[m = l % 16][k = l / 16]
 //   B (4 x 16):  B[k = l / 16][n = l % 16]
 //   D (16 x 16): D[m = 4 * (l / 16) + v][n = l % 16] in accumulator VGPR v.
+#include <type_traits>
+
 #include "act.h"
 #include "tc_internal.h"
 
@@ -203,19 +205,24 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_mfma(ConvArgs a) {
 // Sum of the split-K partials in split order, then bias / LeakyReLU / add / store.
 template <typename T>
 __global__ __launch_bounds__(256) void conv_reduce_kernel(ConvArgs a) {
+  // grid: x over one image's outputs, y = image
+  const int img = blockIdx.y;
   const size_t pixels = (size_t)a.n * a.out_h * a.out_w;
-  const size_t total = pixels * a.cout;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+  const size_t per = (size_t)a.out_h * a.out_w * a.cout;
+  float mx = 0.f;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per;
        i += (size_t)gridDim.x * blockDim.x) {
     const int n = (int)(i % a.cout);
-    const size_t pix = i / a.cout;
+    const size_t pix = (size_t)img * a.out_h * a.out_w + i / a.cout;
     float s = 0.f;
     for (int k = 0; k < a.splits; ++k) s += a.partial[((size_t)k * pixels + pix) * a.np + n];
     const int ox = (int)(pix % a.out_w);
     const int oy = (int)((pix / a.out_w) % a.out_h);
-    const int img = (int)(pix / ((size_t)a.out_w * a.out_h));
-    store_out<T>(a, finish(a, s, n, pix), img, oy, ox, n);
+    const float v = finish(a, s, n, pix);
+    mx = fmaxf(mx, fabsf(v));
+    store_out<T>(a, v, img, oy, ox, n);
   }
+  if (a.aout) record_amax(a.aout + img, mx);
 }
 
 // ---------------------------------------------------------------- head
@@ -325,17 +332,28 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
 // four lane groups of consecutive MFMA steps, so a step can span two taps and
 // no tap is padded to 32 channels.  The weights of a chunk are packed
 // [step][lane group][n][8 k] so one 16-byte LDS read is one B fragment.
-template <int S, int NB, int MR>
+// F8: the same walk with FP8 E4M3 operands (v_mfma_f32_16x16x32_fp8_fp8, 8
+// bytes per lane): the BF16 input is scaled by 448 / max|x| of its image and
+// rounded to FP8 when staged, weights are FP8 per output channel, and the
+// epilogue multiplies the sums back by both scales.
+__device__ inline float amax_of(const AmaxIn& m, int img) {
+  const unsigned* p = img < m.nsplit ? m.a : m.b;
+  if (!p) return 0.f;
+  return __uint_as_float(p[img < m.nsplit ? img : img - m.nsplit]);
+}
+
+template <int S, int NB, int MR, bool F8>
 __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
+  using W = std::conditional_t<F8, u2v, u4>;  // one operand word: 8 values
   constexpr int TH = 4 * MR;
   constexpr int IH = (TH - 1) * S + 3, IW = (TW - 1) * S + 3;
   constexpr int NPOS = IH * IW;
   constexpr int NP = NB * 16;
-  constexpr int NA = BF_CPC * NPOS;        // 16-byte words of input per chunk
-  constexpr int NBW = BF_STEPS * 4 * NP;   // 16-byte words of weights per chunk
+  constexpr int NA = BF_CPC * NPOS;        // operand words of input per chunk
+  constexpr int NBW = BF_STEPS * 4 * NP;   // operand words of weights per chunk
   constexpr int RA = (NA + 255) / 256, RB = (NBW + 255) / 256;
-  __shared__ u4 sA[NA];
-  __shared__ u4 sB[NBW];
+  __shared__ W sA[NA];
+  __shared__ W sB[NBW];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -346,6 +364,14 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
   const int c_begin = split * a.cps;
   const int c_end = min(a.nchunks, c_begin + a.cps);
   const int nblk = a.nblk;
+  float sa = 1.f, inv_sa = 1.f;
+  if constexpr (F8) {
+    const float m = fmaxf(amax_of(a.ain[0], img), fmaxf(amax_of(a.ain[1], img), amax_of(a.ain[2], img)));
+    if (m > 0.f && m < 3.0e38f) {
+      sa = m / kFp8Max;
+      inv_sa = kFp8Max / m;
+    }
+  }
 
   f4 acc[MR][NB];
 #pragma unroll
@@ -353,7 +379,8 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  u4 ra[RA], rb[RB];
+  u4 ra[RA];
+  W rb[RB];
   auto fetch = [&](int ch) {
 #pragma unroll
     for (int j = 0; j < RA; ++j) {
@@ -373,18 +400,26 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
       }
       ra[j] = val;
     }
-    const u4* wsrc = reinterpret_cast<const u4*>(a.w) + (size_t)ch * NBW;
+    const W* wsrc = reinterpret_cast<const W*>(a.w) + (size_t)ch * NBW;
 #pragma unroll
     for (int j = 0; j < RB; ++j) {
       const int i = tid + j * 256;
-      rb[j] = i < NBW ? wsrc[i] : u4{0u, 0u, 0u, 0u};
+      rb[j] = i < NBW ? wsrc[i] : W{};
     }
   };
   auto stash = [&]() {
 #pragma unroll
     for (int j = 0; j < RA; ++j) {
       const int i = tid + j * 256;
-      if (i < NA) sA[i] = ra[j];
+      if (i < NA) {
+        if constexpr (F8) {
+          float v[8];
+          load8(reinterpret_cast<const bf16*>(&ra[j]), v);
+          sA[i] = pack8_fp8(v, inv_sa);
+        } else {
+          sA[i] = ra[j];
+        }
+      }
     }
 #pragma unroll
     for (int j = 0; j < RB; ++j) {
@@ -409,24 +444,29 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
         const bool ok = kb < nk;
         const int tap = ok ? kb / cpc : 0, cbi = ok ? kb - (kb / cpc) * cpc : 0;
         const int p = tap / 3, q = tap - (tap / 3) * 3;
-        bf8 fb[NB];
+        W fb[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          fb[nb] = __builtin_bit_cast(bf8, sB[(st * 4 + lk) * NP + nb * 16 + lm]);
+        for (int nb = 0; nb < NB; ++nb) fb[nb] = sB[(st * 4 + lk) * NP + nb * 16 + lm];
 #pragma unroll
         for (int mb = 0; mb < MR; ++mb) {
           const int r = wave * MR + mb;
-          const bf8 fa =
-              __builtin_bit_cast(bf8, sA[cbi * NPOS + (r * S + p) * IW + lm * S + q]);
+          const W fa = sA[cbi * NPOS + (r * S + p) * IW + lm * S + q];
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb[nb], acc[mb][nb], 0, 0, 0);
+          for (int nb = 0; nb < NB; ++nb) {
+            if constexpr (F8)
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(
+                  __builtin_bit_cast(long, fa), __builtin_bit_cast(long, fb[nb]), acc[mb][nb], 0, 0, 0);
+            else
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  __builtin_bit_cast(bf8, fa), __builtin_bit_cast(bf8, fb[nb]), acc[mb][nb], 0, 0, 0);
+          }
         }
       }
     }
     __syncthreads();
   }
 
+  float mx = 0.f;
 #pragma unroll
   for (int mb = 0; mb < MR; ++mb) {
     const int oy = ty0 + wave * MR + mb;
@@ -435,34 +475,39 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
     for (int nb = 0; nb < NB; ++nb) {
       const int n = nb * 16 + lm;
       if (n >= a.cout) continue;
+      const float osc = F8 ? sa * a.wscale[n] : 1.f;
 #pragma unroll
       for (int vv = 0; vv < 4; ++vv) {
         const int ox = tx0 + 4 * lk + vv;
         if (ox >= a.out_w) continue;
+        const float accv = acc[mb][nb][vv] * osc;
         if (a.splits > 1) {
-          a.partial[((((size_t)split * a.n + img) * a.out_h + oy) * a.out_w + ox) * NP + n] =
-              acc[mb][nb][vv];
+          a.partial[((((size_t)split * a.n + img) * a.out_h + oy) * a.out_w + ox) * NP + n] = accv;
         } else {
           const size_t pix = ((size_t)img * a.out_h + oy) * a.out_w + ox;
-          store_out<bf16>(a, finish(a, acc[mb][nb][vv], n, pix), img, oy, ox, n);
+          const float v = finish(a, accv, n, pix);
+          mx = fmaxf(mx, fabsf(v));
+          store_out<bf16>(a, v, img, oy, ox, n);
         }
       }
     }
   }
+  // all lanes of the wave reach this (split is uniform over the grid)
+  if (a.splits == 1 && a.aout) record_amax(a.aout + img, mx);
 }
 
-template <int S, int MR>
+template <int S, int MR, bool F8>
 hipError_t dispatch_bf16(const ConvArgs& a, hipStream_t s) {
   dim3 grid(cdiv(a.out_w, TW), cdiv(a.out_h, 4 * MR), a.n * a.splits);
   switch (a.np / 16) {
-    case 1: conv3x3_bf16_mfma<S, 1, MR><<<grid, 256, 0, s>>>(a); break;
-    case 2: conv3x3_bf16_mfma<S, 2, MR><<<grid, 256, 0, s>>>(a); break;
-    case 3: conv3x3_bf16_mfma<S, 3, MR><<<grid, 256, 0, s>>>(a); break;
-    case 4: conv3x3_bf16_mfma<S, 4, MR><<<grid, 256, 0, s>>>(a); break;
-    case 5: conv3x3_bf16_mfma<S, 5, MR><<<grid, 256, 0, s>>>(a); break;
-    case 6: conv3x3_bf16_mfma<S, 6, MR><<<grid, 256, 0, s>>>(a); break;
-    case 7: conv3x3_bf16_mfma<S, 7, MR><<<grid, 256, 0, s>>>(a); break;
-    case 8: conv3x3_bf16_mfma<S, 8, MR><<<grid, 256, 0, s>>>(a); break;
+    case 1: conv3x3_bf16_mfma<S, 1, MR, F8><<<grid, 256, 0, s>>>(a); break;
+    case 2: conv3x3_bf16_mfma<S, 2, MR, F8><<<grid, 256, 0, s>>>(a); break;
+    case 3: conv3x3_bf16_mfma<S, 3, MR, F8><<<grid, 256, 0, s>>>(a); break;
+    case 4: conv3x3_bf16_mfma<S, 4, MR, F8><<<grid, 256, 0, s>>>(a); break;
+    case 5: conv3x3_bf16_mfma<S, 5, MR, F8><<<grid, 256, 0, s>>>(a); break;
+    case 6: conv3x3_bf16_mfma<S, 6, MR, F8><<<grid, 256, 0, s>>>(a); break;
+    case 7: conv3x3_bf16_mfma<S, 7, MR, F8><<<grid, 256, 0, s>>>(a); break;
+    case 8: conv3x3_bf16_mfma<S, 8, MR, F8><<<grid, 256, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -525,21 +570,25 @@ hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, int mr, hipStre
   if (a.n <= 0 || a.out_h <= 0 || a.out_w <= 0) return hipSuccess;
   if (a.splits < 1 || a.cps < 1 || (a.splits > 1 && !a.partial)) return hipErrorInvalidValue;
   hipError_t e = hipErrorInvalidValue;
-  if (a.bf16act) {
-    if (stride == 1 && mr == 4) e = dispatch_bf16<1, 4>(a, s);
-    else if (stride == 1 && mr == 2) e = dispatch_bf16<1, 2>(a, s);
-    else if (stride == 2 && mr == 2) e = dispatch_bf16<2, 2>(a, s);
+  if (a.bf16act && a.fp8) {
+    if (stride == 1 && mr == 4) e = dispatch_bf16<1, 4, true>(a, s);
+    else if (stride == 1 && mr == 2) e = dispatch_bf16<1, 2, true>(a, s);
+    else if (stride == 2 && mr == 2) e = dispatch_bf16<2, 2, true>(a, s);
+  } else if (a.bf16act) {
+    if (stride == 1 && mr == 4) e = dispatch_bf16<1, 4, false>(a, s);
+    else if (stride == 1 && mr == 2) e = dispatch_bf16<1, 2, false>(a, s);
+    else if (stride == 2 && mr == 2) e = dispatch_bf16<2, 2, false>(a, s);
   } else if (stride == 1 && kc == 8 && mr == 4) e = dispatch_nb<1, 8, 4>(a, s);
   else if (stride == 1 && kc == 8 && mr == 2) e = dispatch_nb<1, 8, 2>(a, s);
   else if (stride == 2 && kc == 8 && mr == 2) e = dispatch_nb<2, 8, 2>(a, s);
   else if (stride == 2 && kc == 4 && mr == 2) e = dispatch_nb<2, 4, 2>(a, s);
   else if (stride == 1 && kc == 4 && mr == 2) e = dispatch_nb<1, 4, 2>(a, s);
   if (e != hipSuccess || a.splits == 1) return e;
-  const size_t total = (size_t)a.n * a.out_h * a.out_w * a.cout;
+  const dim3 g(grid_1d((size_t)a.out_h * a.out_w * a.cout), a.n);
   if (a.bf16act)
-    conv_reduce_kernel<bf16><<<grid_1d(total), 256, 0, s>>>(a);
+    conv_reduce_kernel<bf16><<<g, 256, 0, s>>>(a);
   else
-    conv_reduce_kernel<float><<<grid_1d(total), 256, 0, s>>>(a);
+    conv_reduce_kernel<float><<<g, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 

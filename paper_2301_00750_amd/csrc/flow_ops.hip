@@ -11,23 +11,36 @@ namespace {
 // T = float: blocks of 4 channels (RGB, 0); T = bf16: blocks of 8 (RGB, 0 x 5).
 template <typename T>
 __global__ __launch_bounds__(256) void stage_kernel(const float* __restrict__ frames, int n, int h,
-                                                    int w, T* __restrict__ out, int hp, int wp) {
-  const size_t total = (size_t)n * hp * wp;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+                                                    int w, T* __restrict__ out, int hp, int wp,
+                                                    unsigned* aout) {
+  // grid: x over the pixels of one image, y = image
+  const int img = blockIdx.y;
+  const size_t per = (size_t)hp * wp;
+  float mx = 0.f;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per;
        i += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(i % wp);
-    const int y = (int)((i / wp) % hp);
-    const int img = (int)(i / ((size_t)wp * hp));
+    const int y = (int)(i / wp);
     const int sy = y < h ? y : h - 1, sx = x < w ? x : w - 1;
     const size_t plane = (size_t)h * w;
     const float* f = frames + (size_t)img * 3 * plane + (size_t)sy * w + sx;
+    const float r = f[0], g = f[plane], b = f[2 * plane];
+    mx = fmaxf(mx, fmaxf(fabsf(r), fmaxf(fabsf(g), fabsf(b))));
+    const size_t o = (size_t)img * per + i;
     if constexpr (sizeof(T) == 4) {
-      *reinterpret_cast<f4*>(out + i * 4) = f4{f[0], f[plane], f[2 * plane], 0.f};
+      *reinterpret_cast<f4*>(out + o * 4) = f4{r, g, b, 0.f};
     } else {
-      const float v[8] = {f[0], f[plane], f[2 * plane], 0.f, 0.f, 0.f, 0.f, 0.f};
-      store8(out + i * 8, v);
+      const float v[8] = {r, g, b, 0.f, 0.f, 0.f, 0.f, 0.f};
+      store8(out + o * 8, v);
     }
   }
+  if (aout) record_amax(aout + img, mx);
+}
+
+__global__ __launch_bounds__(256) void zero_u32_kernel(unsigned* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
 }
 
 // ---------------------------------------------------------------- up2
@@ -187,8 +200,8 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
     }
     __syncthreads();
   }
-  if (!valid) return;
-  if (a.splits > 1) {
+  if (a.splits > 1) {  // uniform over the grid
+    if (!valid) return;
     float* pp = a.partial + ((size_t)(split * a.n + img) * NCV) * h * w + (size_t)y * w + x;
 #pragma unroll
     for (int k = 0; k < NCV; ++k) pp[(size_t)k * h * w] = acc[k];
@@ -196,34 +209,40 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
   }
 
   // Z: blocks of 8 channels, [cv 0..NCV-1 | U_x | U_y | 0 ...]
-  const float invC = 1.f / (float)a.C;
-  float ux = 0.f, uy = 0.f;
-  if (U) {
-    const float2 u = U[(size_t)y * w + x];
-    ux = u.x;
-    uy = u.y;
-  }
-  constexpr int ZCB = (NCV + 2 + 7) / 8;
-  T* z = reinterpret_cast<T*>(a.Z) + (size_t)img * ZCB * plane + ((size_t)y * w + x) * 8;
-#pragma unroll
-  for (int b = 0; b < ZCB; ++b) {
-    float v[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int c = b * 8 + e;
-      float val = 0.f;
-      if (c < NCV) {
-        val = acc[c] * invC;
-        val = val >= 0.f ? val : a.slope * val;
-      } else if (c == NCV) {
-        val = ux;
-      } else if (c == NCV + 1) {
-        val = uy;
-      }
-      v[e] = val;
+  float mx = 0.f;
+  if (valid) {
+    const float invC = 1.f / (float)a.C;
+    float ux = 0.f, uy = 0.f;
+    if (U) {
+      const float2 u = U[(size_t)y * w + x];
+      ux = u.x;
+      uy = u.y;
     }
-    store8(z + (size_t)b * plane, v);
+    constexpr int ZCB = (NCV + 2 + 7) / 8;
+    T* z = reinterpret_cast<T*>(a.Z) + (size_t)img * ZCB * plane + ((size_t)y * w + x) * 8;
+#pragma unroll
+    for (int b = 0; b < ZCB; ++b) {
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int c = b * 8 + e;
+        float val = 0.f;
+        if (c < NCV) {
+          val = acc[c] * invC;
+          val = val >= 0.f ? val : a.slope * val;
+        } else if (c == NCV) {
+          val = ux;
+        } else if (c == NCV + 1) {
+          val = uy;
+        }
+        v[e] = val;
+        mx = fmaxf(mx, fabsf(val));
+      }
+      store8(z + (size_t)b * plane, v);
+    }
   }
+  // every lane of the wave reaches this call (it reduces across the wave)
+  if (a.aout) record_amax(a.aout + img, mx);
 }
 
 // Adds the channel splits of the cost volume in split order and writes Z:
@@ -233,13 +252,14 @@ template <int R, typename T>
 __global__ __launch_bounds__(256) void cv_reduce_kernel(CvArgs a) {
   constexpr int D = 2 * R + 1, NCV = D * D, ZCB = (NCV + 2 + 7) / 8;
   const size_t hw = (size_t)a.h * a.w;
-  const size_t total = (size_t)a.n * ZCB * 8 * hw;
+  const size_t per = (size_t)ZCB * 8 * hw;
+  const int img = blockIdx.y;
   const float invC = 1.f / (float)a.C;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+  float mx = 0.f;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per;
        i += (size_t)gridDim.x * blockDim.x) {
     const size_t pix = i % hw;
-    const int c = (int)((i / hw) % (ZCB * 8));
-    const int img = (int)(i / (hw * ZCB * 8));
+    const int c = (int)(i / hw);
     float val = 0.f;
     if (c < NCV) {
       for (int s = 0; s < a.splits; ++s)
@@ -249,9 +269,11 @@ __global__ __launch_bounds__(256) void cv_reduce_kernel(CvArgs a) {
     } else if (c == NCV || c == NCV + 1) {
       val = a.U ? a.U[((size_t)img * hw + pix) * 2 + (c - NCV)] : 0.f;
     }
+    mx = fmaxf(mx, fabsf(val));
     store1(reinterpret_cast<T*>(a.Z) + ((size_t)img * ZCB + (c >> 3)) * hw * 8 + pix * 8 + (c & 7),
            val);
   }
+  if (a.aout) record_amax(a.aout + img, mx);
 }
 
 int grid_for(size_t total) {
@@ -262,14 +284,21 @@ int grid_for(size_t total) {
 }  // namespace
 
 hipError_t launch_stage(const float* frames, int n, int h, int w, float* out, int hp, int wp,
-                        int bf16act, hipStream_t s) {
-  const size_t total = (size_t)n * hp * wp;
-  if (!total) return hipSuccess;
+                        int bf16act, unsigned* aout, hipStream_t s) {
+  const size_t per = (size_t)hp * wp;
+  if (!per || n <= 0) return hipSuccess;
+  dim3 grid(grid_for(per), n);
   if (bf16act)
-    stage_kernel<bf16><<<grid_for(total), 256, 0, s>>>(frames, n, h, w, reinterpret_cast<bf16*>(out),
-                                                        hp, wp);
+    stage_kernel<bf16><<<grid, 256, 0, s>>>(frames, n, h, w, reinterpret_cast<bf16*>(out), hp, wp,
+                                            aout);
   else
-    stage_kernel<float><<<grid_for(total), 256, 0, s>>>(frames, n, h, w, out, hp, wp);
+    stage_kernel<float><<<grid, 256, 0, s>>>(frames, n, h, w, out, hp, wp, aout);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned* p, size_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  zero_u32_kernel<<<grid_for(n), 256, 0, s>>>(p, n);
   return hipGetLastError();
 }
 
@@ -317,7 +346,7 @@ hipError_t launch_warp_cost_volume(const CvArgs& a, hipStream_t s) {
     warp_cv_kernel<4, float><<<grid, 256, 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.splits == 1) return e;
-  const int g = grid_for((size_t)a.n * a.zcb * 8 * a.h * a.w);
+  const dim3 g(grid_for((size_t)a.zcb * 8 * a.h * a.w), a.n);
   if (a.bf16act)
     cv_reduce_kernel<4, bf16><<<g, 256, 0, s>>>(a);
   else

@@ -38,10 +38,21 @@ struct ConvLayer {
   int cin_pad;     // multiple of kc
   int kc;          // input channels per K chunk (= block size of the input)
   int np;          // cout rounded up to 16
-  float* w;        // device, packed (bfloat16 bits for bfloat16 conv layers)
+  float* w;        // device, packed (bfloat16 / FP8 bits for those layers)
   float* b;        // device, np floats
   int bf16;        // weights packed for conv3x3_bf16_mfma:
                    // [cdiv(cin_pad / 8, BF_CPC)][BF_STEPS][4][np][8] bfloat16
+  int fp8;         // same order, FP8 E4M3 bytes, scaled per output channel by ws
+  float* ws;       // device, np per-output-channel weight scales (FP8 layers)
+};
+
+// Per-image absolute-maximum slots (float bits as unsigned) of an activation
+// tensor: image img < nsplit uses a[img], else b[img - nsplit].  Producers
+// fold their outputs into them; FP8 consumers derive their input scale.
+struct AmaxIn {
+  const unsigned* a;
+  const unsigned* b;
+  int nsplit;
 };
 
 struct ConvArgs {
@@ -66,6 +77,10 @@ struct ConvArgs {
   int splits, cps;
   float* partial;
   int bf16act;  // input and (blocked) output activations stored as bfloat16
+  int fp8;      // FP8 E4M3 MFMA: inputs scaled by max(ain) / 448, weights by wscale
+  AmaxIn ain[3];
+  const float* wscale;  // per output channel (np)
+  unsigned* aout;       // per-image amax of the outputs, or null
 };
 
 // Launch plan of one conv: rows per wave (tile = 4 * mr rows x 16 columns)
@@ -84,7 +99,10 @@ hipError_t launch_head(const ConvArgs& a, hipStream_t s);
 // NCHW float frames (n x 3 x h x w) -> one channel block per pixel, bottom /
 // right edge replicated: float32 blocks of 4 (RGB, 0) or bfloat16 blocks of 8.
 hipError_t launch_stage(const float* frames, int n, int h, int w, float* out, int hp, int wp,
-                        int bf16act, hipStream_t s);
+                        int bf16act, unsigned* aout, hipStream_t s);
+
+// Sets n unsigned words to zero (amax slots before a pass).
+hipError_t launch_zero_u32(unsigned* p, size_t n, hipStream_t s);
 
 // U = 2 * up2(flow), both compact NHWC with 2 channels: (n, h, w) -> (n, 2h, 2w).
 hipError_t launch_up2x2(const float* flow, int n, int h, int w, float* U, hipStream_t s);
@@ -106,6 +124,7 @@ struct CvArgs {
   int splits, cps;
   float* partial;
   int bf16act;  // features and Z stored as bfloat16
+  unsigned* aout;  // per-image amax of the cost-volume outputs, or null
 };
 struct CvPlan {
   int splits, cps;

@@ -25,6 +25,7 @@ EXPORTS = (
     "tc_flow_workspace_bytes", "tc_flow_estimate", "tc_flow_estimate_pair",
     "tc_consistency_step", "tc_probe_enable", "tc_probe_read", "tc_probe_disable",
     "tc_paper_default_params", "tc_paper_workspace_bytes", "tc_consistency_paper",
+    "tc_fp8_e4m3_encode",
 )
 
 TC_OP_PYR_A, TC_OP_PYR_B, TC_OP_UP2, TC_OP_COST_VOLUME, TC_OP_C1, TC_OP_C2, TC_OP_C3, TC_OP_HEAD = range(8)
@@ -89,6 +90,7 @@ def _load():
         "tc_probe_disable": (None, []),
         "tc_paper_default_params": (None, [ctypes.POINTER(PaperParams)]),
         "tc_paper_workspace_bytes": (sz, [ci, ci, ci]),
+        "tc_fp8_e4m3_encode": (None, [vp, vp, sz]),
         "tc_consistency_paper": (ci, [vp] * 9 + [ctypes.POINTER(PaperParams), ci, ci, ci, vp, vp,
                                                  sz, vp]),
     }

@@ -402,3 +402,54 @@ def test_paper_consistency_fixed_point_and_zero_clamps(tc):
     assert torch.allclose(out, args[4], atol=1e-5, rtol=0)
     with pytest.raises(tc.TcError):
         tc.consistency_paper(*args, params=tc.paper_params(k1=0.7, k2=0.5))
+
+
+# ---------------------------------------------------------------- FP8 E4M3 precision form
+
+
+@pytest.mark.parametrize("levels", [1, 4])
+def test_fp8_flow_tiny_vs_oracle(tc, levels):
+    d = sub_desc(synth.load_desc("tiny"), levels)
+    blob = synth.he_weights(d)
+    wts = O.unpack_weights(blob, d)
+    net = tc.Net(d, blob, precision=tc.TC_FP8_E4M3)
+    prev, cur, _, _ = synth.tiny_pair()
+    say(f"[fp8 flow] tiny levels={levels}")
+    fw, bw = net.flow_estimate_pair(g(prev[None]), g(cur[None]))
+    torch.cuda.synchronize()
+    rfw, rbw = O.flow_pair(f64(prev), f64(cur), wts, d)
+    for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
+        mean, mx = flow_err(a, b)
+        say(f"   {name}: EPE mean={mean:.3e} max={mx:.3e}")
+        assert mean <= 0.25
+
+
+def test_fp8_batch_invariance_and_determinism(tc, tiny):
+    d, blob, wts, _ = tiny
+    net = tc.Net(d, blob, precision=tc.TC_FP8_E4M3)
+    gen = torch.Generator().manual_seed(23)
+    A = torch.rand(2, 3, 90, 150, generator=gen)
+    B = torch.rand(2, 3, 90, 150, generator=gen)
+    fw, bw = net.flow_estimate_pair(g(A), g(B))
+    fw2, bw2 = net.flow_estimate_pair(g(A), g(B))
+    s1 = net.flow_estimate_pair(g(A[1:]), g(B[1:]))
+    torch.cuda.synchronize()
+    assert torch.equal(fw, fw2) and torch.equal(bw, bw2)
+    assert torch.equal(s1[0][0], fw[1]) and torch.equal(s1[1][0], bw[1])
+
+
+def test_fp8_fullhd_pair_vs_oracle(tc):
+    d = synth.load_desc("fullhd")
+    blob = synth.he_weights(d)
+    wts = O.unpack_weights(blob, d)
+    net = tc.Net(d, blob, precision=tc.TC_FP8_E4M3)
+    sc = synth.LayeredScene(1920, 1080, seed=0)
+    I0, I1 = sc.frame(0), sc.frame(1)
+    say("[fp8 flow] 1920x1080 pair")
+    fw, bw = net.flow_estimate_pair(g(I0[None]), g(I1[None]))
+    torch.cuda.synchronize()
+    rfw, rbw = O.flow_pair(f64(I0), f64(I1), wts, d)
+    for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
+        mean, mx = flow_err(a, b)
+        say(f"   {name}: EPE mean={mean:.3e} max={mx:.3e}")
+        assert mean <= 0.25

@@ -103,3 +103,26 @@ def test_flow_argument_checks(tc):
     assert L.tc_flow_estimate(None, p, p, 1, 8, 8, p, p, 1 << 20, None) == tc.TC_ERR_INVALID_ARG
     assert L.tc_pyramid_bytes(None, 1, 8, 8) == 0
     assert L.tc_flow_workspace_bytes(None, 1, 8, 8) == 0
+
+
+def test_fp8_encoder_matches_torch_e4m3fn(tc):
+    """The host FP8 encoder of the weights equals torch's float8_e4m3fn cast
+    (round to nearest even) on normal, subnormal, tie and boundary values;
+    beyond 448 it saturates where torch would give NaN."""
+    import torch
+    rng = np.random.default_rng(3)
+    vals = np.concatenate([
+        rng.standard_normal(4000) * 10, rng.standard_normal(2000) * 1e-2,
+        rng.uniform(-448, 448, 2000), 2.0 ** -np.arange(0, 12),
+        [0.0, -0.0, 448.0, -448.0, 240.0, 0.001953125, 0.0009765625, 1.0625, 1.125 * 1.0625],
+        (np.arange(1, 64) + 0.5) * 2.0 ** -9,   # subnormal ties
+        (np.arange(8, 16) + 0.5) * 2.0 ** -3,   # normal ties
+    ]).astype(np.float32)
+    out = np.empty(vals.size, np.uint8)
+    tc.lib().tc_fp8_e4m3_encode(vals.ctypes.data, out.ctypes.data, vals.size)
+    ref = torch.from_numpy(vals).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    assert np.array_equal(out, ref)
+    big = np.array([449.0, 1000.0, -5e5], np.float32)
+    o2 = np.empty(3, np.uint8)
+    tc.lib().tc_fp8_e4m3_encode(big.ctypes.data, o2.ctypes.data, 3)
+    assert list(o2) == [0x7e, 0x7e, 0xfe]
