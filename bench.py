@@ -166,6 +166,8 @@ def main():
                     help="comma-separated precision forms measured after the FP32 path ('' = none)")
     ap.add_argument("--paper-steps", type=int, default=30,
                     help="1080p frames of the paper's full consistency step to time (0 = skip)")
+    ap.add_argument("--serve-frames", type=int, default=90,
+                    help="frames per stream of the 16-stream serving mix (0 = skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="before timing, run 3 plain device copies of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -281,12 +283,54 @@ def main():
         result["paper_consistency"] = paper_leg(tcflow, nets["fp32"], I, P, args.paper_steps,
                                                 r["ms"])
 
+    if args.serve_frames > 0:
+        result["serving"] = serve_leg(tcflow, desc, blob, args.serve_frames)
+
     if args.cpu_frames > 0:
         result["cpu_baseline"], epe = cpu_leg(nets, desc, I, P, args.cpu_frames)
         result["epe_vs_oracle"] = epe.pop("fp32")
         for form, e in epe.items():
             result["precision_forms"][form]["epe_vs_oracle"] = e
     print(json.dumps(result), flush=True)
+
+
+def serve_leg(tcflow, desc, blob, nframes, unique=6):
+    """16 concurrent streams, 4 each at 640x360, 1280x720, 1920x1080 and
+    3840x2160, Poisson frame arrivals at 30 frames/s per stream, BF16 net,
+    continuous batching per resolution (paper_2301_00750_amd.serve)."""
+    from paper_2301_00750_amd import serve
+    dev = torch.device("cuda:0")
+    net = tcflow.Net(desc, blob, precision=tcflow.TC_BF16)
+    res = [(360, 640), (720, 1280), (1080, 1920), (2160, 3840)]
+    jobs = []
+    for ri, (h, w) in enumerate(res):
+        for k in range(4):
+            sid = 4 * ri + k
+            sc = synth.LayeredScene(w, h, seed=100 + sid)
+            I = [sc.frame(t, device=dev)[None].contiguous() for t in range(unique)]
+            P = [synth.stylize(x[0], t)[None].contiguous() for t, x in enumerate(I)]
+            jobs.append(serve.StreamJob(sid, I, P, serve.poisson_arrivals(nframes, 30.0, 1000 + sid),
+                                        alpha=0.5))
+    torch.cuda.synchronize()
+    free = torch.cuda.mem_get_info(dev)[0]
+    srv = serve.Server(net, int(0.8 * free))
+    log(f"serving: 16 streams x {nframes} frames")
+    summary = srv.run(jobs)
+    per = {}
+    for ri, (h, w) in enumerate(res):
+        lat = np.concatenate([np.asarray(j.latencies_ms) for j in jobs[4 * ri:4 * ri + 4]])
+        per[f"{w}x{h}"] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                           "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+    return {
+        "what": "16 streams (4 each at 640x360, 1280x720, 1920x1080, 3840x2160), Poisson arrivals "
+                f"at 30 frames/s per stream, {nframes} frames each, BF16, continuous batching",
+        "offered_frames_per_s": 16 * 30,
+        "aggregate_frames_per_s": round(summary["frames_per_s"], 2),
+        "p50_latency_ms": round(summary["p50_ms"], 3),
+        "p99_latency_ms": round(summary["p99_ms"], 3),
+        "per_resolution": per,
+        "wall_s": round(summary["wall_s"], 3),
+    }
 
 
 def paper_leg(tcflow, net, I, P, steps, flow_ms):

@@ -114,6 +114,17 @@ TC_API int tc_flow_from_pyramids(const tc_net* net, const void* pyr1, const void
                                  int h, int w, float* flow12, float* flow21, void* ws,
                                  size_t ws_bytes, void* stream);
 
+/* Continuous batching over streams: one decoder pass for n (<= 16) frame
+ * pairs whose pyramids live in separate one-image buffers (tc_pyramid with
+ * n = 1 and the same h, w): flow_fw[i] = flow(prev i -> cur i),
+ * flow_bw[i] = flow(cur i -> prev i), each 1 x 2 x h x w.  Every image is
+ * computed exactly as in a one-pair call.  TC_FP32 and TC_BF16 nets. */
+TC_API size_t tc_decoder_list_workspace_bytes(const tc_net* net, int n, int h, int w);
+TC_API int tc_flow_from_pyramid_list(const tc_net* net, const void* const* pyr_prev,
+                                     const void* const* pyr_cur, int n, int h, int w,
+                                     float* const* flow_fw, float* const* flow_bw, void* ws,
+                                     size_t ws_bytes, void* stream);
+
 /* Scratch bytes of tc_flow_estimate / tc_flow_estimate_pair (two pyramids
  * plus the decoder scratch). */
 TC_API size_t tc_flow_workspace_bytes(const tc_net* net, int n, int h, int w);

@@ -299,6 +299,7 @@ View plain_view(const float* p, int cbt, int cb0 = 0) {
   v.nsplit = 1 << 30;
   v.cbt = cbt;
   v.cb0 = cb0;
+  v.tab = nullptr;
   return v;
 }
 
@@ -395,9 +396,17 @@ int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, cha
   return TC_OK;
 }
 
+// Per-image buffers of a batched decoder pass over separately stored pyramids:
+// device tables (in the workspace) of level bases and output flows.
+struct ListTables {
+  const void* const* tab[9];  // per level: F1 bases of the nb images, then F2 bases
+  float* const* out;          // nb output flows
+};
+
 // Decoder pass over nb = n (one direction) or 2n (both) images.
 int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, int h, int w,
-                float* flow12, float* flow21, char* ws, hipStream_t s) {
+                float* flow12, float* flow21, char* ws, hipStream_t s,
+                const ListTables* lists = nullptr) {
   const tc_net_desc& d = net->d;
   const LevelDims g = dims(d, h, w);
   const PyrLayout p = pyr_layout(net, n, h, w);
@@ -414,20 +423,24 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
     return dslots ? dslots + (size_t)dec_slot(l, which) * nb : nullptr;
   };
   const unsigned* pslots1 =
-      net->fp8 ? reinterpret_cast<const unsigned*>(pyr1 + p.slots) : nullptr;
+      (net->fp8 && pyr1) ? reinterpret_cast<const unsigned*>(pyr1 + p.slots) : nullptr;
   const unsigned* pslots2 =
-      net->fp8 ? reinterpret_cast<const unsigned*>(pyr2 + p.slots) : nullptr;
+      (net->fp8 && pyr2) ? reinterpret_cast<const unsigned*>(pyr2 + p.slots) : nullptr;
   if (dslots) TC_TRY_HIP(launch_zero_u32(dslots, (size_t)3 * d.levels * nb, s));
   const AmaxIn none{nullptr, nullptr, 0};
   const int d0b = d.dec[0] / 8, d1b = d.dec[1] / 8, d23b = (d.dec[1] + d.dec[2]) / 8;
   int cur = 0;
   for (int l = d.levels; l >= 1; --l) {
     const int C = d.ch[l - 1], hl = g.h[l], wl = g.w[l];
-    const float* P1 = reinterpret_cast<const float*>(pyr1 + p.off[l]);
-    const float* P2 = reinterpret_cast<const float*>(pyr2 + p.off[l]);
+    const float* P1 = pyr1 ? reinterpret_cast<const float*>(pyr1 + p.off[l]) : nullptr;
+    const float* P2 = pyr2 ? reinterpret_cast<const float*>(pyr2 + p.off[l]) : nullptr;
     View f1, f2;
-    f1.a = P1; f1.b = P2; f1.nsplit = n; f1.cbt = C / 8; f1.cb0 = 0;
-    f2.a = P2; f2.b = P1; f2.nsplit = n; f2.cbt = C / 8; f2.cb0 = 0;
+    f1.a = P1; f1.b = P2; f1.nsplit = n; f1.cbt = C / 8; f1.cb0 = 0; f1.tab = nullptr;
+    f2.a = P2; f2.b = P1; f2.nsplit = n; f2.cbt = C / 8; f2.cb0 = 0; f2.tab = nullptr;
+    if (lists) {  // per-image pyramids: tables [F1 of 2n images | F2 of 2n images]
+      f1.tab = lists->tab[l];
+      f2.tab = lists->tab[l] + nb;
+    }
     const float* Ul = nullptr;
     if (l < d.levels) {
       probe_begin(TC_STAGE(l, TC_OP_UP2), s);
@@ -483,7 +496,8 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
     cur = nxt;
   }
   probe_begin(TC_STAGE_OUTPUT, s);
-  TC_TRY_HIP(launch_final_flow(flows[cur], nb, g.h[1], g.w[1], flow12, flow21, n, h, w, s));
+  TC_TRY_HIP(launch_final_flow(flows[cur], nb, g.h[1], g.w[1], flow12, flow21, n, h, w,
+                                lists ? lists->out : nullptr, s));
   probe_end(TC_STAGE_OUTPUT, s);
   return TC_OK;
 }
@@ -689,6 +703,60 @@ int tc_flow_from_pyramids(const tc_net* net, const void* pyr1, const void* pyr2,
   if (ws_bytes < dec_layout(net, flow21 ? 2 * n : n, h, w).total) return TC_ERR_WORKSPACE;
   return run_decoder(net, static_cast<const char*>(pyr1), static_cast<const char*>(pyr2), n, h, w,
                      flow12, flow21, static_cast<char*>(ws), (hipStream_t)stream);
+}
+
+size_t tc_decoder_list_workspace_bytes(const tc_net* net, int n, int h, int w) {
+  if (!net || !shape_ok(n, h, w) || n > kTabMax / 4) return 0;
+  const size_t tables = (size_t)(net->d.levels * 4 * n + 2 * n) * sizeof(void*);
+  return dec_layout(net, 2 * n, h, w).total + align_up(tables, kAlign);
+}
+
+int tc_flow_from_pyramid_list(const tc_net* net, const void* const* pyr_prev,
+                              const void* const* pyr_cur, int n, int h, int w,
+                              float* const* flow_fw, float* const* flow_bw, void* ws,
+                              size_t ws_bytes, void* stream) {
+  if (!net || !pyr_prev || !pyr_cur || !flow_fw || !flow_bw || !ws || !shape_ok(n, h, w))
+    return TC_ERR_INVALID_ARG;
+  if (n > kTabMax / 4) return TC_ERR_UNSUPPORTED;
+  if (net->fp8) return TC_ERR_UNSUPPORTED;
+  for (int i = 0; i < n; ++i)
+    if (!pyr_prev[i] || !pyr_cur[i] || !flow_fw[i] || !flow_bw[i] || !aligned(pyr_prev[i]) ||
+        !aligned(pyr_cur[i]))
+      return TC_ERR_INVALID_ARG;
+  if (!aligned(ws) || ws_bytes < tc_decoder_list_workspace_bytes(net, n, h, w))
+    return TC_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const PyrLayout p = pyr_layout(net, 1, h, w);  // each listed pyramid holds one image
+  const DecLayout D = dec_layout(net, 2 * n, h, w);
+  char* base = static_cast<char*>(ws);
+  const void** tabs = reinterpret_cast<const void**>(base + D.total);
+  ListTables lt;
+  // images [0, n) decode prev -> cur (forward), [n, 2n) cur -> prev (backward)
+  for (int l = 1; l <= net->d.levels; ++l) {
+    PtrTable t;
+    for (int i = 0; i < n; ++i) {
+      const char* a = static_cast<const char*>(pyr_prev[i]) + p.off[l];
+      const char* b = static_cast<const char*>(pyr_cur[i]) + p.off[l];
+      t.p[i] = a;          // F1, forward
+      t.p[n + i] = b;      // F1, backward
+      t.p[2 * n + i] = b;  // F2, forward
+      t.p[3 * n + i] = a;  // F2, backward
+    }
+    const void** dst = tabs + (size_t)(l - 1) * 4 * n;
+    TC_TRY_HIP(launch_write_table(t, 4 * n, dst, s));
+    lt.tab[l] = dst;
+  }
+  {
+    PtrTable t;
+    for (int i = 0; i < n; ++i) {
+      t.p[i] = flow_fw[i];
+      t.p[n + i] = flow_bw[i];
+    }
+    const void** dst = tabs + (size_t)net->d.levels * 4 * n;
+    TC_TRY_HIP(launch_write_table(t, 2 * n, dst, s));
+    lt.out = reinterpret_cast<float* const*>(reinterpret_cast<void*>(dst));
+  }
+  return run_decoder(net, nullptr, nullptr, n, h, w, flow_fw[0], flow_bw[0], base, s, &lt);
 }
 
 size_t tc_flow_workspace_bytes(const tc_net* net, int n, int h, int w) {

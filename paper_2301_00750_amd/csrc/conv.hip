@@ -33,12 +33,14 @@ constexpr int TW = 16;
 __host__ __device__ constexpr int pitch16(int n) { return (n % 32 == 16) ? n : (n / 32) * 32 + 48; }
 
 __device__ inline const float* view_base(const View& v, int img, size_t img_floats) {
+  if (v.tab) return reinterpret_cast<const float*>(v.tab[img]);
   return img < v.nsplit ? v.a + (size_t)img * img_floats
                         : v.b + (size_t)(img - v.nsplit) * img_floats;
 }
 
 template <typename T>
 __device__ inline const T* view_base_t(const View& v, int img, size_t img_elems) {
+  if (v.tab) return reinterpret_cast<const T*>(v.tab[img]);
   return img < v.nsplit ? reinterpret_cast<const T*>(v.a) + (size_t)img * img_elems
                         : reinterpret_cast<const T*>(v.b) + (size_t)(img - v.nsplit) * img_elems;
 }

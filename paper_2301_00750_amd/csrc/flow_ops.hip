@@ -37,6 +37,10 @@ __global__ __launch_bounds__(256) void stage_kernel(const float* __restrict__ fr
   if (aout) record_amax(aout + img, mx);
 }
 
+__global__ void write_table_kernel(PtrTable t, int n, const void** dst) {
+  if ((int)threadIdx.x < n) dst[threadIdx.x] = t.p[threadIdx.x];
+}
+
 __global__ __launch_bounds__(256) void zero_u32_kernel(unsigned* p, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x)
@@ -80,7 +84,7 @@ __global__ __launch_bounds__(256) void up2x2_kernel(const float* __restrict__ fl
 __global__ __launch_bounds__(256) void final_flow_kernel(const float* __restrict__ flow1, int n,
                                                          int h1, int w1, float* __restrict__ out_a,
                                                          float* __restrict__ out_b, int nsplit,
-                                                         int H, int W) {
+                                                         int H, int W, float* const* out_tab) {
   const size_t total = (size_t)n * H * W;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
        i += (size_t)gridDim.x * blockDim.x) {
@@ -95,7 +99,9 @@ __global__ __launch_bounds__(256) void final_flow_kernel(const float* __restrict
     const float2 a = f[y0 * w1 + x0], b = f[y0 * w1 + x1], c = f[y1 * w1 + x0], d = f[y1 * w1 + x1];
     const float rx = 2.f * ((1.f - fy) * ((1.f - fx) * a.x + fx * b.x) + fy * ((1.f - fx) * c.x + fx * d.x));
     const float ry = 2.f * ((1.f - fy) * ((1.f - fx) * a.y + fx * b.y) + fy * ((1.f - fx) * c.y + fx * d.y));
-    float* o = img < nsplit ? out_a + (size_t)img * 2 * H * W : out_b + (size_t)(img - nsplit) * 2 * H * W;
+    float* o = out_tab ? out_tab[img]
+               : img < nsplit ? out_a + (size_t)img * 2 * H * W
+                              : out_b + (size_t)(img - nsplit) * 2 * H * W;
     o[(size_t)y * W + x] = rx;
     o[(size_t)H * W + (size_t)y * W + x] = ry;
   }
@@ -114,6 +120,7 @@ constexpr int CV_TY = 8, CV_TX = 32;
 
 template <typename T>
 __device__ inline const T* vbase(const View& v, int img, size_t img_elems) {
+  if (v.tab) return reinterpret_cast<const T*>(v.tab[img]);
   return img < v.nsplit ? reinterpret_cast<const T*>(v.a) + (size_t)img * img_elems
                         : reinterpret_cast<const T*>(v.b) + (size_t)(img - v.nsplit) * img_elems;
 }
@@ -310,10 +317,18 @@ hipError_t launch_up2x2(const float* flow, int n, int h, int w, float* U, hipStr
 }
 
 hipError_t launch_final_flow(const float* flow1, int n, int h1, int w1, float* out_a, float* out_b,
-                             int nsplit, int H, int W, hipStream_t s) {
+                             int nsplit, int H, int W, float* const* out_tab, hipStream_t s) {
   const size_t total = (size_t)n * H * W;
   if (!total) return hipSuccess;
-  final_flow_kernel<<<grid_for(total), 256, 0, s>>>(flow1, n, h1, w1, out_a, out_b, nsplit, H, W);
+  final_flow_kernel<<<grid_for(total), 256, 0, s>>>(flow1, n, h1, w1, out_a, out_b, nsplit, H, W,
+                                                    out_tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_write_table(const PtrTable& t, int n, const void** dst, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n > kTabMax) return hipErrorInvalidValue;
+  write_table_kernel<<<1, kTabMax, 0, s>>>(t, n, dst);
   return hipGetLastError();
 }
 

@@ -17,14 +17,24 @@ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 // so a block of B channels of one pixel is contiguous and neighbouring pixels
 // are neighbouring in memory.  B = 8 everywhere except the staged RGB frame
 // (B = 4).  A view may split its batch over two buffers: images [0, nsplit)
-// come from `a`, the rest from `b` (index img - nsplit).
+// come from `a`, the rest from `b` (index img - nsplit); or, when `tab` is
+// set, image img lives in its own buffer tab[img] (a device-resident table).
 struct View {
   const float* a;
   const float* b;
   int nsplit;
   int cbt;  // blocks per image in the underlying buffer
   int cb0;  // first block of the view
+  const void* const* tab;
 };
+
+// Copies up to kTabMax pointers (carried in the kernel arguments) into a
+// device-resident table.
+constexpr int kTabMax = 64;
+struct PtrTable {
+  const void* p[kTabMax];
+};
+hipError_t launch_write_table(const PtrTable& t, int n, const void** dst, hipStream_t s);
 
 // BF16 conv: channel blocks of 8 per K chunk and MFMA steps per full chunk.
 constexpr int BF_CPC = 2;
@@ -136,7 +146,8 @@ hipError_t launch_warp_cost_volume(const CvArgs& a, hipStream_t s);
 // Output: flow NCHW (n x 2 x H x W) = crop(2 * up2(flow1)); flow1 NHWC
 // (n x h1 x w1 x 2).  Images [0, nsplit) go to out_a, the rest to out_b.
 hipError_t launch_final_flow(const float* flow1, int n, int h1, int w1, float* out_a,
-                             float* out_b, int nsplit, int H, int W, hipStream_t s);
+                             float* out_b, int nsplit, int H, int W, float* const* out_tab,
+                             hipStream_t s);
 
 // The paper's consistency step (Eq. 1-8).  Frames NCHW (n x 3 x h x w),
 // flows n x 2 x h x w: f_tp = flow from t to t-1, f_tn = flow from t to t+1.

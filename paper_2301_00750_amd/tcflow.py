@@ -25,7 +25,7 @@ EXPORTS = (
     "tc_flow_workspace_bytes", "tc_flow_estimate", "tc_flow_estimate_pair",
     "tc_consistency_step", "tc_probe_enable", "tc_probe_read", "tc_probe_disable",
     "tc_paper_default_params", "tc_paper_workspace_bytes", "tc_consistency_paper",
-    "tc_fp8_e4m3_encode",
+    "tc_fp8_e4m3_encode", "tc_decoder_list_workspace_bytes", "tc_flow_from_pyramid_list",
 )
 
 TC_OP_PYR_A, TC_OP_PYR_B, TC_OP_UP2, TC_OP_COST_VOLUME, TC_OP_C1, TC_OP_C2, TC_OP_C3, TC_OP_HEAD = range(8)
@@ -91,6 +91,9 @@ def _load():
         "tc_paper_default_params": (None, [ctypes.POINTER(PaperParams)]),
         "tc_paper_workspace_bytes": (sz, [ci, ci, ci]),
         "tc_fp8_e4m3_encode": (None, [vp, vp, sz]),
+        "tc_decoder_list_workspace_bytes": (sz, [vp, ci, ci, ci]),
+        "tc_flow_from_pyramid_list": (ci, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ci, ci, ci,
+                                           ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp]),
         "tc_consistency_paper": (ci, [vp] * 9 + [ctypes.POINTER(PaperParams), ci, ci, ci, vp, vp,
                                                  sz, vp]),
     }
@@ -193,6 +196,19 @@ class Net:
             self._h, _ptr(pyr1), _ptr(pyr2), n, h, w, _ptr(f12), _ptr(f21), _ptr(ws),
             ws.numel() * ws.element_size(), _stream(stream)))
         return (f12, f21) if both else f12
+
+    def decoder_list_workspace_bytes(self, n, h, w):
+        return _lib.tc_decoder_list_workspace_bytes(self._h, n, h, w)
+
+    def flow_from_pyramid_list(self, pyr_prev, pyr_cur, h, w, fw, bw, ws, stream=None):
+        """One batched decoder pass over per-stream one-image pyramids
+        (tc_flow_from_pyramid_list); fw[i], bw[i] are 1 x 2 x h x w outputs."""
+        n = len(pyr_prev)
+        arr = ctypes.c_void_p * n
+        _check("tc_flow_from_pyramid_list", _lib.tc_flow_from_pyramid_list(
+            self._h, arr(*[p.data_ptr() for p in pyr_prev]), arr(*[p.data_ptr() for p in pyr_cur]),
+            n, h, w, arr(*[f.data_ptr() for f in fw]), arr(*[f.data_ptr() for f in bw]), _ptr(ws),
+            ws.numel() * ws.element_size(), _stream(stream)))
 
     def flow_estimate(self, prev, cur, ws=None, out=None, stream=None):
         _frames(prev, "prev", 3)
