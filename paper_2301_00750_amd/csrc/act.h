@@ -72,15 +72,39 @@ __device__ inline u2v pack8_fp8(const float (&v)[8], float inv_scale) {
   return u2v{(unsigned)lo, (unsigned)hi};
 }
 
-// Wave-wide maximum folded into a per-image slot (values are >= 0, so their
-// float bit patterns order like unsigned integers).  Maximum is independent
-// of the order in which waves arrive.
-__device__ inline void record_amax(unsigned* slot, float v) {
-  if (!slot) return;
+// Each image's absolute maximum is spread over kAmaxSub sub-slots, each on
+// its own 128-byte line, so that the workgroups of a kernel do not all hit
+// one address; a consumer takes the maximum of the sub-slots.
+constexpr int kAmaxSub = 64;
+constexpr int kAmaxStride = 32;  // unsigned words between sub-slots
+constexpr int kAmaxWords = kAmaxSub * kAmaxStride;  // per image
+
+// Workgroup-wide maximum folded into one of the image's sub-slots with one
+// atomic (values are >= 0, so their float bit patterns order like unsigned
+// integers; the maximum is independent of arrival order).  Every thread of
+// the workgroup (blockDim.x <= 1024) must call this.
+__device__ inline void record_amax(unsigned* slots, float v) {
+  __shared__ float red[16];
+  if (!slots) return;
   v = fabsf(v);
   if (!(v <= 3.0e38f)) v = 3.0e38f;  // NaN / inf saturate
   for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-  if ((threadIdx.x & 63) == 0) atomicMax(slot, __float_as_uint(v));
+  const int wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < nw; ++i) v = fmaxf(v, red[i]);
+    const unsigned sub = (blockIdx.x * 7u + blockIdx.y * 13u + blockIdx.z * 29u) % kAmaxSub;
+    atomicMax(slots + sub * kAmaxStride, __float_as_uint(v));
+  }
+}
+
+// Maximum over an image's sub-slots; every lane of the wave must call this.
+__device__ inline float read_amax(const unsigned* slots) {
+  if (!slots) return 0.f;
+  float v = __uint_as_float(slots[(threadIdx.x & (kAmaxSub - 1)) * kAmaxStride]);
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
 }
 
 }  // namespace tc

@@ -97,8 +97,10 @@ struct PyrLayout {
   size_t stage, tmp, partial, slots, total;
 };
 
-// amax slots (n unsigned each): stage, then per level tmp and features
-inline size_t pyr_slot(int n, int which) { return (size_t)which * n; }
+// amax slots (n images x kAmaxSub unsigned each): stage, then per level tmp
+// and features
+constexpr int kSub = 64 * 32;  // words per image (kAmaxWords of the kernels)
+inline size_t pyr_slot(int n, int which) { return (size_t)which * n * kSub; }
 inline int pyr_slot_stage() { return 0; }
 inline int pyr_slot_tmp(int l) { return 1 + 2 * (l - 1); }
 inline int pyr_slot_feat(int l) { return 2 + 2 * (l - 1); }
@@ -137,7 +139,7 @@ PyrLayout pyr_layout(const tc_net* net, int n, int h, int w) {
   p.partial = pos;
   pos = align_up(pos + part, kAlign);
   p.slots = pos;
-  pos = align_up(pos + (size_t)(1 + 2 * d.levels) * n * sizeof(unsigned), kAlign);
+  pos = align_up(pos + (size_t)(1 + 2 * d.levels) * n * kSub * sizeof(unsigned), kAlign);
   p.total = pos;
   return p;
 }
@@ -177,7 +179,7 @@ DecLayout dec_layout(const tc_net* net, int nb, int h, int w) {
     if (pb > part) part = pb;
   }
   L.partial = take(part);
-  L.slots = take((size_t)3 * net->d.levels * nb * sizeof(unsigned));
+  L.slots = take((size_t)3 * net->d.levels * nb * kSub * sizeof(unsigned));
   L.total = pos;
   return L;
 }
@@ -363,10 +365,9 @@ int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, cha
   float* part = reinterpret_cast<float*>(pyr + p.partial);
   unsigned* slots = net->fp8 ? reinterpret_cast<unsigned*>(pyr + p.slots) : nullptr;
   auto slot = [&](int which) { return slots ? slots + pyr_slot(n, which) : nullptr; };
-  if (slots) TC_TRY_HIP(launch_zero_u32(slots, (size_t)(1 + 2 * d.levels) * n, s));
+  if (slots) TC_TRY_HIP(launch_zero_u32(slots, (size_t)(1 + 2 * d.levels) * n * kSub, s));
   probe_begin(TC_STAGE_INPUT, s);
-  TC_TRY_HIP(launch_stage(frames, n, h, w, stage, g.hp, g.wp, net->bf16act, slot(pyr_slot_stage()),
-                          s));
+  TC_TRY_HIP(launch_stage(frames, n, h, w, stage, g.hp, g.wp, net->bf16act, nullptr, s));
   probe_end(TC_STAGE_INPUT, s);
   const float* in = stage;
   int in_cbt = 1, in_h = g.hp, in_w = g.wp;
@@ -381,12 +382,12 @@ int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, cha
     int st = conv_layer(La, plain_view(in, in_cbt), La.cin_pad / ((La.bf16 || La.fp8) ? 8 : La.kc),
                         plain_view(in, in_cbt), in_h, in_w, tmp, C / 8, 0, 0, nullptr, g.h[l], g.w[l],
                         1, d.leaky, n, 2, TC_STAGE(l, TC_OP_PYR_A), part, net->bf16act, ain_a,
-                        slot(pyr_slot_tmp(l)), s);
+                        nullptr, s);
     if (st) return st;
     st = conv_layer(net->pyr[l - 1][1], plain_view(tmp, C / 8), C / 8, plain_view(tmp, C / 8),
                     g.h[l], g.w[l], feat, C / 8, 0, 0, nullptr, g.h[l], g.w[l], 1, d.leaky, n, 1,
-                    TC_STAGE(l, TC_OP_PYR_B), part, net->bf16act, ain_b, slot(pyr_slot_feat(l)),
-                    s);
+                    TC_STAGE(l, TC_OP_PYR_B), part, net->bf16act, ain_b,
+                    net->dec[l - 1][0].fp8 ? slot(pyr_slot_feat(l)) : nullptr, s);
     if (st) return st;
     in = feat;
     in_cbt = C / 8;
@@ -420,13 +421,13 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
   float* part = reinterpret_cast<float*>(ws + D.partial);
   unsigned* dslots = net->fp8 ? reinterpret_cast<unsigned*>(ws + D.slots) : nullptr;
   auto dslot = [&](int l, int which) {
-    return dslots ? dslots + (size_t)dec_slot(l, which) * nb : nullptr;
+    return dslots ? dslots + (size_t)dec_slot(l, which) * nb * kSub : nullptr;
   };
   const unsigned* pslots1 =
       (net->fp8 && pyr1) ? reinterpret_cast<const unsigned*>(pyr1 + p.slots) : nullptr;
   const unsigned* pslots2 =
       (net->fp8 && pyr2) ? reinterpret_cast<const unsigned*>(pyr2 + p.slots) : nullptr;
-  if (dslots) TC_TRY_HIP(launch_zero_u32(dslots, (size_t)3 * d.levels * nb, s));
+  if (dslots) TC_TRY_HIP(launch_zero_u32(dslots, (size_t)3 * d.levels * nb * kSub, s));
   const AmaxIn none{nullptr, nullptr, 0};
   const int d0b = d.dec[0] / 8, d1b = d.dec[1] / 8, d23b = (d.dec[1] + d.dec[2]) / 8;
   int cur = 0;
@@ -465,7 +466,7 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
     cv.cps = cp.cps;
     cv.partial = part;
     cv.bf16act = net->bf16act;
-    cv.aout = dslot(l, 0);
+    cv.aout = net->dec[l - 1][0].fp8 ? dslot(l, 0) : nullptr;
     probe_begin(TC_STAGE(l, TC_OP_COST_VOLUME), s);
     TC_TRY_HIP(launch_warp_cost_volume(cv, s));
     probe_end(TC_STAGE(l, TC_OP_COST_VOLUME), s);
@@ -478,11 +479,11 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
     const AmaxIn ain_c3[3] = {amax_plain(dslot(l, 2)), none, none};
     int st = conv_layer(L[0], f1, C / 8, plain_view(Z, net->zcb), hl, wl, H1, d0b, 0, 0, nullptr,
                         hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C1), part, net->bf16act,
-                        ain_c1, dslot(l, 1), s);
+                        ain_c1, L[1].fp8 ? dslot(l, 1) : nullptr, s);
     if (st) return st;
     st = conv_layer(L[1], plain_view(H1, d0b), d0b, plain_view(H1, d0b), hl, wl, H23, d23b, 0, 0,
                     nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C2), part, net->bf16act,
-                    ain_c2, dslot(l, 2), s);
+                    ain_c2, L[2].fp8 ? dslot(l, 2) : nullptr, s);
     if (st) return st;
     st = conv_layer(L[2], plain_view(H23, d23b), d1b, plain_view(H23, d23b), hl, wl, H23, d23b,
                     d1b, 0, nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C3), part, net->bf16act,

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void conv_reduce_kernel(ConvArgs a) {
     mx = fmaxf(mx, fabsf(v));
     store_out<T>(a, v, img, oy, ox, n);
   }
-  if (a.aout) record_amax(a.aout + img, mx);
+  if (a.aout) record_amax(a.aout + (size_t)img * kAmaxWords, mx);
 }
 
 // ---------------------------------------------------------------- head
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
 __device__ inline float amax_of(const AmaxIn& m, int img) {
   const unsigned* p = img < m.nsplit ? m.a : m.b;
   if (!p) return 0.f;
-  return __uint_as_float(p[img < m.nsplit ? img : img - m.nsplit]);
+  return read_amax(p + (size_t)(img < m.nsplit ? img : img - m.nsplit) * kAmaxWords);
 }
 
 template <int S, int NB, int MR, bool F8>
@@ -495,7 +495,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
     }
   }
   // all lanes of the wave reach this (split is uniform over the grid)
-  if (a.splits == 1 && a.aout) record_amax(a.aout + img, mx);
+  if (a.splits == 1 && a.aout) record_amax(a.aout + (size_t)img * kAmaxWords, mx);
 }
 
 template <int S, int MR, bool F8>

@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void stage_kernel(const float* __restrict__ fr
       store8(out + o * 8, v);
     }
   }
-  if (aout) record_amax(aout + img, mx);
+  if (aout) record_amax(aout + (size_t)img * kAmaxWords, mx);
 }
 
 __global__ void write_table_kernel(PtrTable t, int n, const void** dst) {
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
     }
   }
   // every lane of the wave reaches this call (it reduces across the wave)
-  if (a.aout) record_amax(a.aout + img, mx);
+  if (a.aout) record_amax(a.aout + (size_t)img * kAmaxWords, mx);
 }
 
 // Adds the channel splits of the cost volume in split order and writes Z:
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void cv_reduce_kernel(CvArgs a) {
     store1(reinterpret_cast<T*>(a.Z) + ((size_t)img * ZCB + (c >> 3)) * hw * 8 + pix * 8 + (c & 7),
            val);
   }
-  if (a.aout) record_amax(a.aout + img, mx);
+  if (a.aout) record_amax(a.aout + (size_t)img * kAmaxWords, mx);
 }
 
 int grid_for(size_t total) {
