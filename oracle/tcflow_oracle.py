@@ -29,12 +29,20 @@ Stylizing Video Streams"):
   fine) with "light" estimators that keep a dense connection only into the
   last layer.
 * Supplementary Eq. S1: the end-point error.
+* Sec. 3.2, "Optimized Network Architecture", and the supplementary ablation
+  of the flow estimators and the refinement: the network variant without the
+  estimator of the finest level (its flow, at the next level, is upsampled
+  bilinearly to the input size) and the refinement network whose standard
+  convolutions are replaced by depthwise separable ones ("-sepref").
 
 Parity status: every op (pad, conv, LeakyReLU, up2, warp, cost volume, mask,
 blend) is pinned by tests/test_oracle.py against closed forms, brute force,
 library routines and exact invariants; the level recursion and the decoder's
 channel order are pinned with constructed weights.  The composition of the
 random-weight network as a whole has no published value to pin against.
+The variants' ops (integer-factor upsampling, dilated depthwise and pointwise
+convs) and their composition (input order, dilation per layer, dropped level,
+output scale) are pinned by tests/test_oracle_variants.py.
 """
 from __future__ import annotations
 
@@ -49,27 +57,34 @@ def unpack_weights(blob, desc):
 
     Blob layout, layer after layer: W[cout][cin][3][3] then b[cout].  Order:
     pyramid convs of level 1..L (stride 2 then stride 1), then the decoder of
-    level 1..L (c1, c2, c3, head).
+    every level that has one, f..L with f = desc["finest"] (c1, c2, c3, head),
+    then the separable refinement layers: a depthwise 3x3 W[c][3][3], b[c],
+    then a pointwise W[cout][cin], b[cout].
     """
     L, ch, dec, r = desc["levels"], desc["ch"], desc["dec"], desc["radius"]
     ncv = (2 * r + 1) * (2 * r + 1)
     names = []
     for l in range(1, L + 1):
-        names.append((f"pyr{l}a", ch[l - 1], 3 if l == 1 else ch[l - 2]))
-        names.append((f"pyr{l}b", ch[l - 1], ch[l - 1]))
-    for l in range(1, L + 1):
-        names.append((f"dec{l}c1", dec[0], ncv + ch[l - 1] + 2))
-        names.append((f"dec{l}c2", dec[1], dec[0]))
-        names.append((f"dec{l}c3", dec[2], dec[1]))
-        names.append((f"dec{l}head", 2, dec[1] + dec[2]))
+        names.append((f"pyr{l}a", (ch[l - 1], 3 if l == 1 else ch[l - 2], 3, 3)))
+        names.append((f"pyr{l}b", (ch[l - 1], ch[l - 1], 3, 3)))
+    for l in range(desc.get("finest", 1), L + 1):
+        names.append((f"dec{l}c1", (dec[0], ncv + ch[l - 1] + 2, 3, 3)))
+        names.append((f"dec{l}c2", (dec[1], dec[0], 3, 3)))
+        names.append((f"dec{l}c3", (dec[2], dec[1], 3, 3)))
+        names.append((f"dec{l}head", (2, dec[1] + dec[2], 3, 3)))
+    width = dec[1] + dec[2] + 2
+    for j, co in enumerate((desc.get("refine") or {}).get("ch", []), start=1):
+        names.append((f"ref{j}dw", (width, 3, 3)))
+        names.append((f"ref{j}pw", (co, width)))
+        width = co
     blob = np.asarray(blob, dtype=np.float64).ravel()
     out, pos = {}, 0
-    for name, co, ci in names:
-        n = co * ci * 9
-        w = blob[pos:pos + n].reshape(co, ci, 3, 3)
+    for name, shape in names:
+        n = int(np.prod(shape))
+        w = blob[pos:pos + n].reshape(shape)
         pos += n
-        b = blob[pos:pos + co]
-        pos += co
+        b = blob[pos:pos + shape[0]]
+        pos += shape[0]
         out[name] = (w, b)
     if pos != blob.size:
         raise ValueError(f"weight blob has {blob.size} floats, layout needs {pos}")
@@ -135,6 +150,24 @@ def up2(f):
     """
     def axis_taps(n):
         src = np.clip((np.arange(2 * n) + 0.5) / 2.0 - 0.5, 0.0, n - 1)
+        i0 = np.floor(src).astype(np.int64)
+        i1 = np.minimum(i0 + 1, n - 1)
+        return i0, i1, src - i0
+
+    C, h, w = f.shape
+    r0, r1, ry = axis_taps(h)
+    c0, c1, rx = axis_taps(w)
+    rows = f[:, r0, :] * (1 - ry)[None, :, None] + f[:, r1, :] * ry[None, :, None]
+    return rows[:, :, c0] * (1 - rx)[None, None, :] + rows[:, :, c1] * rx[None, None, :]
+
+
+def upsample(f, s):
+    """Bilinear upsampling by an integer factor s, half-pixel centres
+    (align_corners=False): output index i samples the input at
+    (i + 1/2)/s - 1/2, clamped to [0, n-1].  (C, h, w) -> (C, s h, s w).
+    For s = 2 this is up2."""
+    def axis_taps(n):
+        src = np.clip((np.arange(s * n) + 0.5) / s - 0.5, 0.0, n - 1)
         i0 = np.floor(src).astype(np.int64)
         i1 = np.minimum(i0 + 1, n - 1)
         return i0, i1, src - i0
@@ -228,13 +261,14 @@ def pyramid(img_padded, wts, desc):
     return feats
 
 
-def decode_level(l, F1, F2, U, wts, desc):
+def decode_level(l, F1, F2, U, wts, desc, features=False):
     """One light flow estimator at level l.
 
     Warp the second image's features by the upsampled flow U, correlate with
     the first image's features, and estimate a flow increment from
     [cost volume | F1 | U] with three conv layers; the head sees the last two
-    layers' outputs [h2 | h3].  Returns flow_l = U + increment.
+    layers' outputs [h2 | h3].  Returns flow_l = U + increment (and, with
+    ``features``, also h2 and h3).
     """
     slope = desc["leaky"]
     F2w = warp_zero(F2, U)
@@ -244,22 +278,73 @@ def decode_level(l, F1, F2, U, wts, desc):
     h2 = lrelu(conv3x3(h1, *wts[f"dec{l}c2"]), slope)
     h3 = lrelu(conv3x3(h2, *wts[f"dec{l}c3"]), slope)
     delta = conv3x3(np.concatenate([h2, h3], axis=0), *wts[f"dec{l}head"])
+    if features:
+        return U + delta, h2, h3
     return U + delta
+
+
+def depthwise3x3(x, w, b, dilation):
+    """Depthwise 3x3 cross-correlation with the given dilation, zero padding:
+    y[c, i, j] = b[c] + sum_{p,q} w[c, p, q] x[c, i + (p-1) d, j + (q-1) d]."""
+    C, H, W = x.shape
+    d = dilation
+    xp = np.zeros((C, H + 2 * d, W + 2 * d))
+    xp[:, d:d + H, d:d + W] = x
+    y = np.repeat(np.asarray(b, np.float64)[:, None, None], H, axis=1).repeat(W, axis=2)
+    for p in range(3):
+        for q in range(3):
+            y = y + w[:, p, q][:, None, None] * xp[:, p * d:p * d + H, q * d:q * d + W]
+    return y
+
+
+def pointwise(x, w, b):
+    """1x1 convolution: y[o] = b[o] + sum_c w[o, c] x[c]."""
+    C, H, W = x.shape
+    return (w @ x.reshape(C, H * W) + np.asarray(b)[:, None]).reshape(-1, H, W)
+
+
+def refine(h2, h3, flow_f, wts, desc):
+    """Separable refinement ("context") network on the finest estimator.
+
+    Input [h2 | h3 | flow]; each layer is a depthwise 3x3 conv with its
+    dilation, bias and LeakyReLU, then a pointwise conv with bias (LeakyReLU
+    on all but the last layer, which outputs 2 channels); the result is added
+    to the flow (Sec. 3.2, the "-sepref" design: the refinement's standard
+    convolutions replaced by depthwise separable ones).
+    """
+    slope = desc["leaky"]
+    dils = desc["refine"]["dil"]
+    x = np.concatenate([h2, h3, flow_f], axis=0)
+    for j, d in enumerate(dils, start=1):
+        x = lrelu(depthwise3x3(x, *wts[f"ref{j}dw"], d), slope)
+        x = pointwise(x, *wts[f"ref{j}pw"])
+        if j < len(dils):
+            x = lrelu(x, slope)
+    return flow_f + x
 
 
 def flow_from_pyramids(P1, P2, wts, desc, out_hw):
     """Coarse-to-fine flow from image 1 to image 2 given both pyramids.
 
-    U_L = 0; U_l = 2 up2(flow_{l+1}); output crop(2 up2(flow_1)) in pixels of
-    the input resolution, cropped to ``out_hw``.
+    U_L = 0; U_l = 2 up2(flow_{l+1}) down to the finest estimator level f
+    (1, or 2 with the finest estimator dropped); optionally refined; output
+    crop(2^f upsample(flow_f, 2^f)) in pixels of the input resolution,
+    cropped to ``out_hw``.
     """
     L = desc["levels"]
+    f = desc.get("finest", 1)
+    has_ref = bool((desc.get("refine") or {}).get("ch"))
     flow = None
-    for l in range(L, 0, -1):
+    for l in range(L, f - 1, -1):
         F1, F2 = P1[l - 1], P2[l - 1]
         U = np.zeros((2,) + F1.shape[1:]) if flow is None else 2.0 * up2(flow)
-        flow = decode_level(l, F1, F2, U, wts, desc)
-    full = 2.0 * up2(flow)
+        if l == f and has_ref:
+            flow, h2, h3 = decode_level(l, F1, F2, U, wts, desc, features=True)
+            flow = refine(h2, h3, flow, wts, desc)
+        else:
+            flow = decode_level(l, F1, F2, U, wts, desc)
+    s = 2 ** f
+    full = s * upsample(flow, s)
     H, W = out_hw
     return full[:, :H, :W]
 

@@ -6,7 +6,7 @@ and the HIP path receive the very same arrays from it.
 
 Contents
   * ``load_desc(name)``       network/workload descriptor (JSON under configs/).
-  * ``layer_shapes(desc)``    (cout, cin) of every 3x3 conv in blob order.
+  * ``layer_shapes(desc)``    (name, cout, cin, taps) of every conv in blob order.
   * ``he_weights(desc)``      one flat float32 blob of He-normal weights.
   * ``tiny_pair()``           periodic value-noise frame and its copy rolled by
                               an integer flow (the 128x96 workload).
@@ -18,10 +18,14 @@ Contents
                               frame, which is what the method removes).
 
 Weight blob layout (float32, little endian), layer after layer:
-  W[cout][cin][3][3] followed by b[cout].
+  W[cout][cin][taps] followed by b[cout]  (taps = 9 for a 3x3 kernel, 1 for a
+  pointwise one; a depthwise layer has cin = 1).
 Layer order: for level l = 1..L the two pyramid convs (stride 2: C_{l-1}->C_l,
-then stride 1: C_l->C_l, with C_0 = 3); then for level l = 1..L the decoder
-c1 (81+C_l+2 -> d1), c2 (d1 -> d2), c3 (d2 -> d3), head (d2+d3 -> 2).
+then stride 1: C_l->C_l, with C_0 = 3); then for each level l = f..L that has
+an estimator (f = ``finest``, 1 unless the finest estimator is dropped) the
+decoder c1 (81+C_l+2 -> d1), c2 (d1 -> d2), c3 (d2 -> d3), head (d2+d3 -> 2);
+then for each refinement layer j = 1..R its depthwise 3x3 (c_{j-1} channels,
+c_0 = d2+d3+2) and its pointwise 1x1 (c_{j-1} -> c_j).
 """
 from __future__ import annotations
 
@@ -42,39 +46,58 @@ def load_desc(name: str) -> dict:
         return json.load(f)
 
 
+def finest(desc: dict) -> int:
+    """Finest level with a flow estimator (2 when the finest one is dropped)."""
+    return int(desc.get("finest", 1))
+
+
+def refine_layers(desc: dict) -> list:
+    """[(width, dilation)] of the separable refinement network (may be empty)."""
+    r = desc.get("refine") or {}
+    return list(zip(r.get("ch", []), r.get("dil", [])))
+
+
 def layer_shapes(desc: dict) -> list:
-    """(name, cout, cin) of every conv in blob order."""
+    """(name, cout, cin, taps) of every conv in blob order."""
     L, ch, dec = desc["levels"], desc["ch"], desc["dec"]
     ncv = (2 * desc["radius"] + 1) ** 2
     out = []
     for l in range(1, L + 1):
         cin = 3 if l == 1 else ch[l - 2]
-        out.append((f"pyr{l}a", ch[l - 1], cin))
-        out.append((f"pyr{l}b", ch[l - 1], ch[l - 1]))
-    for l in range(1, L + 1):
+        out.append((f"pyr{l}a", ch[l - 1], cin, 9))
+        out.append((f"pyr{l}b", ch[l - 1], ch[l - 1], 9))
+    for l in range(finest(desc), L + 1):
         din = ncv + ch[l - 1] + 2
-        out.append((f"dec{l}c1", dec[0], din))
-        out.append((f"dec{l}c2", dec[1], dec[0]))
-        out.append((f"dec{l}c3", dec[2], dec[1]))
-        out.append((f"dec{l}head", 2, dec[1] + dec[2]))
+        out.append((f"dec{l}c1", dec[0], din, 9))
+        out.append((f"dec{l}c2", dec[1], dec[0], 9))
+        out.append((f"dec{l}c3", dec[2], dec[1], 9))
+        out.append((f"dec{l}head", 2, dec[1] + dec[2], 9))
+    cin = dec[1] + dec[2] + 2
+    for j, (co, _) in enumerate(refine_layers(desc), start=1):
+        out.append((f"ref{j}dw", cin, 1, 9))
+        out.append((f"ref{j}pw", co, cin, 1))
+        cin = co
     return out
 
 
 def blob_floats(desc: dict) -> int:
-    return sum(co * ci * 9 + co for _, co, ci in layer_shapes(desc))
+    return sum(co * ci * k + co for _, co, ci, k in layer_shapes(desc))
 
 
 def he_weights(desc: dict, seed: int | None = None) -> np.ndarray:
-    """He-normal weights, std = sqrt(2 / (9 * cin)), zero biases.
+    """He-normal weights, std = sqrt(2 / fan_in) with fan_in = taps * cin, zero
+    biases.
 
     Drawn with ``numpy.random.default_rng(seed)`` layer by layer in blob order.
-    The head layers are additionally scaled by ``desc['head_gain']``.
+    The layers that output a flow (the estimator heads and the last
+    refinement layer) are additionally scaled by ``desc['head_gain']``.
     """
     rng = np.random.default_rng(desc.get("weight_seed", 0) if seed is None else seed)
+    shapes = layer_shapes(desc)
     parts = []
-    for name, co, ci in layer_shapes(desc):
-        w = rng.standard_normal((co, ci, 3, 3)) * math.sqrt(2.0 / (9 * ci))
-        if name.endswith("head"):
+    for i, (name, co, ci, k) in enumerate(shapes):
+        w = rng.standard_normal((co, ci, k)) * math.sqrt(2.0 / (k * ci))
+        if name.endswith("head") or (name.startswith("ref") and i == len(shapes) - 1):
             w = w * desc.get("head_gain", 1.0)
         parts.append(w.astype(np.float32).ravel())
         parts.append(np.zeros(co, np.float32))
