@@ -47,13 +47,23 @@ typedef enum { TC_FP32 = 0, TC_BF16 = 1, TC_FP8_E4M3 = 2 } tc_precision;
 /* Network descriptor.  levels L in [1, 8]; ch[l-1] = channels of pyramid
  * level l (multiples of 8, at most 128); dec = widths of the three decoder
  * conv layers (multiples of 16, at most 128); radius = cost-volume radius
- * (4 gives 81 displacements); leaky = LeakyReLU slope. */
+ * (4 gives 81 displacements); leaky = LeakyReLU slope.
+ * Variants of Sec. 3.2 ("Optimized Network Architecture"): finest = the
+ * finest level with a flow estimator, in [1, L] (1: every level; 2: the
+ * finest estimator removed, the flow of level 2 is upsampled to the input);
+ * ref_layers in [0, 8] depthwise separable refinement layers ("-sepref") on
+ * that level, layer j with ref_ch[j] outputs (multiples of 8, at most 128;
+ * the last one 2) and dilation ref_dil[j] in [1, 64]. */
 typedef struct {
   int levels;
   int ch[8];
   int dec[3];
   int radius;
   float leaky;
+  int finest;
+  int ref_layers;
+  int ref_ch[8];
+  int ref_dil[8];
 } tc_net_desc;
 
 typedef struct tc_net tc_net; /* opaque */
@@ -69,8 +79,11 @@ TC_API void tc_fp8_e4m3_encode(const float* in, unsigned char* out, size_t n);
 /* Number of float32 values of the weight blob for `desc`.  Blob layout,
  * layer after layer: W[cout][cin][3][3] then b[cout]; order: pyramid convs
  * of level 1..L (stride 2: C_{l-1} -> C_l with C_0 = 3, then stride 1:
- * C_l -> C_l), then the decoders of level 1..L: c1 ((2r+1)^2 + C_l + 2 ->
- * dec0), c2 (dec0 -> dec1), c3 (dec1 -> dec2), head (dec1 + dec2 -> 2). */
+ * C_l -> C_l), then the decoders of level finest..L: c1 ((2r+1)^2 + C_l + 2
+ * -> dec0), c2 (dec0 -> dec1), c3 (dec1 -> dec2), head (dec1 + dec2 -> 2),
+ * then per refinement layer j: depthwise W[c][3][3], b[c] and pointwise
+ * W[ref_ch[j]][c], b[ref_ch[j]] (c = dec1 + dec2 + 2 for j = 0, else
+ * ref_ch[j-1]). */
 TC_API size_t tc_weight_floats(const tc_net_desc* desc);
 
 /* Copies the host weight blob to the current HIP device, packed for the
@@ -105,11 +118,14 @@ TC_API size_t tc_decoder_workspace_bytes(const tc_net* net, int n, int h, int w)
 
 /* Coarse-to-fine flow from the frames of pyramid `pyr1` to those of `pyr2`
  * (flow12, n x 2 x h x w) and, if flow21 is not NULL, the opposite direction
- * in the same batched pass.  Per level l = L..1: U = 2 up2(flow_{l+1})
- * (U_L = 0), warp the second pyramid's features by U, 81-channel cost
- * volume, light estimator on [cost volume | F1 | U] -> increment,
- * flow_l = U + increment; output = 2 up2(flow_1) cropped to h x w.  Paper,
- * Sec. 3.2 and supplementary S1. */
+ * in the same batched pass.  Per level l = L..f (f = desc.finest):
+ * U = 2 up2(flow_{l+1}) (U_L = 0), warp the second pyramid's features by U,
+ * 81-channel cost volume, light estimator on [cost volume | F1 | U] ->
+ * increment, flow_l = U + increment; with refinement layers,
+ * flow_f += refine([h2 | h3 | flow_f]) (each layer: dilated depthwise 3x3,
+ * bias, LeakyReLU, pointwise, bias, LeakyReLU except on the last); output =
+ * 2^f upsample(flow_f, 2^f) (bilinear, half-pixel centres) cropped to h x w.
+ * Paper, Sec. 3.2 and supplementary S1. */
 TC_API int tc_flow_from_pyramids(const tc_net* net, const void* pyr1, const void* pyr2, int n,
                                  int h, int w, float* flow12, float* flow21, void* ws,
                                  size_t ws_bytes, void* stream);
@@ -204,7 +220,8 @@ enum {
   TC_OP_C1 = 4,          /* decoder convs of level l                  */
   TC_OP_C2 = 5,
   TC_OP_C3 = 6,
-  TC_OP_HEAD = 7
+  TC_OP_HEAD = 7,
+  TC_OP_REFINE = 8       /* all refinement layers (level = finest)    */
 };
 #define TC_STAGE_INPUT 1        /* frame staging (pad + relayout)       */
 #define TC_STAGE_OUTPUT 2       /* final upsample + crop of the flow     */

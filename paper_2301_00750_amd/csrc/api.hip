@@ -22,7 +22,8 @@ struct tc_net {
   int ncv;          // (2r+1)^2
   int zcb;          // blocks of the cost-volume buffer (ncv + 2, rounded up to 8)
   ConvLayer pyr[8][2];
-  ConvLayer dec[8][4];
+  ConvLayer dec[8][4];  // levels below d.finest have no estimator (unused)
+  SepLayer ref[8];      // refinement layers 0 .. d.ref_layers - 1
   void* dmem;
 };
 
@@ -64,6 +65,17 @@ bool desc_ok(const tc_net_desc* d) {
   if ((d->dec[1] + d->dec[2]) % 8) return false;
   if (d->radius != 4) return false;
   if (!(d->leaky >= 0.f && d->leaky <= 1.f)) return false;
+  if (d->finest < 1 || d->finest > d->levels) return false;
+  if (d->ref_layers < 0 || d->ref_layers > 8) return false;
+  int width = d->dec[1] + d->dec[2] + 2;
+  for (int j = 0; j < d->ref_layers; ++j) {
+    const bool last = j == d->ref_layers - 1;
+    if (cdiv(width, 32) * 32 > kSepMaxC) return false;
+    if (last ? d->ref_ch[j] != 2 : (d->ref_ch[j] <= 0 || d->ref_ch[j] % 8 || d->ref_ch[j] > 128))
+      return false;
+    if (d->ref_dil[j] < 1 || d->ref_dil[j] > 64) return false;
+    width = d->ref_ch[j];
+  }
   return true;
 }
 
@@ -146,7 +158,7 @@ PyrLayout pyr_layout(const tc_net* net, int n, int h, int w) {
 
 // ---- decoder scratch for a batch of nb images (n pairs -> nb = 2n)
 struct DecLayout {
-  size_t flow[2], U, Z, H1, H23, partial, slots, total;
+  size_t flow[2], U, Z, H1, H23, R[2], partial, slots, total;
 };
 // decoder amax slots (nb unsigned each): per level Z, H1, H2
 inline int dec_slot(int l, int which) { return 3 * (l - 1) + which; }
@@ -154,7 +166,8 @@ inline int dec_slot(int l, int which) { return 3 * (l - 1) + which; }
 DecLayout dec_layout(const tc_net* net, int nb, int h, int w) {
   DecLayout L;
   LevelDims g = dims(net->d, h, w);
-  const size_t px = (size_t)nb * g.h[1] * g.w[1];
+  const int f = net->d.finest;
+  const size_t px = (size_t)nb * g.h[f] * g.w[f];
   size_t pos = 0;
   auto take = [&](size_t bytes) {
     size_t o = pos;
@@ -167,13 +180,17 @@ DecLayout dec_layout(const tc_net* net, int nb, int h, int w) {
   L.Z = take(px * net->zcb * 8 * net->esz);
   L.H1 = take(px * net->d.dec[0] * net->esz);
   L.H23 = take(px * (net->d.dec[1] + net->d.dec[2]) * net->esz);
+  int rw = 0;  // widest refinement activation (the last layer writes a flow)
+  for (int j = 0; j + 1 < net->d.ref_layers; ++j) rw = std::max(rw, net->d.ref_ch[j]);
+  L.R[0] = take(px * rw * net->esz);
+  L.R[1] = take(px * rw * net->esz);
   size_t part = 0;
-  for (int l = 1; l <= net->d.levels; ++l)
+  for (int l = f; l <= net->d.levels; ++l)
     for (int k = 0; k < 3; ++k) {
       const size_t pb = layer_partial_bytes(net->dec[l - 1][k], g.h[l], g.w[l], nb, 1);
       if (pb > part) part = pb;
     }
-  for (int l = 1; l <= net->d.levels; ++l) {
+  for (int l = f; l <= net->d.levels; ++l) {
     const size_t pb = cost_volume_partial_bytes(plan_cost_volume(g.h[l], g.w[l], net->d.ch[l - 1]),
                                                 nb, g.h[l], g.w[l]);
     if (pb > part) part = pb;
@@ -292,6 +309,48 @@ void pack_conv_fp8(const float* W, const float* b, int cout, int cin, int cin_pa
     }
   }
   for (int o = 0; o < cout; ++o) bout[o] = b[o];
+}
+
+// Refinement layer packing.  Pointwise weights: per K chunk (16 channels for
+// FP32, 32 for BF16), per 16-channel output block and lane l, the K/4 values
+// W[16 nb + l % 16][K c + (K/4) (l / 16) + e] (float, or bfloat16), i.e. one
+// MFMA B fragment per lane; zero for padded channels.  Input channels keep
+// the order of the blob.
+struct SepPacked {
+  std::vector<char> pw;
+  std::vector<float> rest;  // b [np], depthwise W [9][cin_pad], depthwise b [cin_pad]
+};
+
+void pack_sep(const SepLayer& L, const float* dw, const float* dwb, const float* pw,
+              const float* pb, SepPacked& out) {
+  const int K = L.bf16 ? 32 : 16, per = K / 4, nch = L.cin_pad / K, nbk = L.np / 16;
+  const size_t nval = (size_t)nch * nbk * 64 * per;
+  std::vector<float> wf(nval, 0.f);
+  for (int c = 0; c < nch; ++c)
+    for (int nb = 0; nb < nbk; ++nb)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < per; ++e) {
+          const int o = nb * 16 + (l & 15), ch = c * K + per * (l >> 4) + e;
+          if (o < L.cout && ch < L.cin)
+            wf[(((size_t)c * nbk + nb) * 64 + l) * per + e] = pw[(size_t)o * L.cin + ch];
+        }
+  if (L.bf16) {
+    out.pw.resize(nval * 2);
+    for (size_t i = 0; i < nval; ++i) {
+      const uint16_t v = host_f2bf(wf[i]);
+      memcpy(out.pw.data() + 2 * i, &v, 2);
+    }
+  } else {
+    out.pw.resize(nval * 4);
+    memcpy(out.pw.data(), wf.data(), nval * 4);
+  }
+  out.rest.assign((size_t)L.np + 10 * L.cin_pad, 0.f);
+  for (int o = 0; o < L.cout; ++o) out.rest[o] = pb[o];
+  float* dwo = out.rest.data() + L.np;
+  for (int c = 0; c < L.cin; ++c) {
+    for (int tap = 0; tap < 9; ++tap) dwo[(size_t)tap * L.cin_pad + c] = dw[(size_t)c * 9 + tap];
+    dwo[(size_t)9 * L.cin_pad + c] = dwb[c];
+  }
 }
 
 View plain_view(const float* p, int cbt, int cb0 = 0) {
@@ -431,7 +490,8 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
   const AmaxIn none{nullptr, nullptr, 0};
   const int d0b = d.dec[0] / 8, d1b = d.dec[1] / 8, d23b = (d.dec[1] + d.dec[2]) / 8;
   int cur = 0;
-  for (int l = d.levels; l >= 1; --l) {
+  const int fl = d.finest;
+  for (int l = d.levels; l >= fl; --l) {
     const int C = d.ch[l - 1], hl = g.h[l], wl = g.w[l];
     const float* P1 = pyr1 ? reinterpret_cast<const float*>(pyr1 + p.off[l]) : nullptr;
     const float* P2 = pyr2 ? reinterpret_cast<const float*>(pyr2 + p.off[l]) : nullptr;
@@ -496,8 +556,34 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
     if (st) return st;
     cur = nxt;
   }
+  if (d.ref_layers > 0) {
+    // refinement on [h2 | h3 | flow_f] (H23 still holds the finest level's
+    // h2 and h3); the last layer writes flow_f + increment
+    const int hl = g.h[fl], wl = g.w[fl];
+    char* R[2] = {ws + D.R[0], ws + D.R[1]};
+    probe_begin(TC_STAGE(fl, TC_OP_REFINE), s);
+    for (int j = 0; j < d.ref_layers; ++j) {
+      const bool last = j == d.ref_layers - 1;
+      SepArgs a;
+      a.in = j == 0 ? static_cast<const void*>(H23) : R[(j - 1) & 1];
+      a.in_cbt = j == 0 ? d23b : d.ref_ch[j - 1] / 8;
+      a.nblk = a.in_cbt;
+      a.flow = j == 0 ? flows[cur] : nullptr;
+      a.n = nb;
+      a.h = hl;
+      a.w = wl;
+      a.slope = d.leaky;
+      a.lrelu = last ? 0 : 1;
+      a.out = last ? static_cast<void*>(flows[cur ^ 1]) : R[j & 1];
+      a.out_cbt = last ? 0 : d.ref_ch[j] / 8;
+      a.add = last ? flows[cur] : nullptr;
+      TC_TRY_HIP(launch_sepconv(net->ref[j], a, s));
+    }
+    probe_end(TC_STAGE(fl, TC_OP_REFINE), s);
+    cur ^= 1;
+  }
   probe_begin(TC_STAGE_OUTPUT, s);
-  TC_TRY_HIP(launch_final_flow(flows[cur], nb, g.h[1], g.w[1], flow12, flow21, n, h, w,
+  TC_TRY_HIP(launch_final_flow(flows[cur], nb, g.h[fl], g.w[fl], 1 << fl, flow12, flow21, n, h, w,
                                 lists ? lists->out : nullptr, s));
   probe_end(TC_STAGE_OUTPUT, s);
   return TC_OK;
@@ -521,7 +607,7 @@ const char* tc_status_str(int st) {
   }
 }
 
-const char* tc_version(void) { return "tcflow 0.3 (gfx950; FP32, BF16 and FP8 E4M3 MFMA)"; }
+const char* tc_version(void) { return "tcflow 0.4 (gfx950; FP32, BF16 and FP8 E4M3 MFMA)"; }
 
 void tc_fp8_e4m3_encode(const float* in, unsigned char* out, size_t n) {
   if (!in || !out) return;
@@ -536,9 +622,14 @@ size_t tc_weight_floats(const tc_net_desc* d) {
     const int cin = l == 1 ? 3 : d->ch[l - 2];
     n += conv_floats(d->ch[l - 1], cin) + conv_floats(d->ch[l - 1], d->ch[l - 1]);
   }
-  for (int l = 1; l <= d->levels; ++l) {
+  for (int l = d->finest; l <= d->levels; ++l) {
     n += conv_floats(d->dec[0], ncv + d->ch[l - 1] + 2) + conv_floats(d->dec[1], d->dec[0]) +
          conv_floats(d->dec[2], d->dec[1]) + conv_floats(2, d->dec[1] + d->dec[2]);
+  }
+  int width = d->dec[1] + d->dec[2] + 2;
+  for (int j = 0; j < d->ref_layers; ++j) {
+    n += (size_t)width * 9 + width + (size_t)d->ref_ch[j] * width + d->ref_ch[j];
+    width = d->ref_ch[j];
   }
   return n;
 }
@@ -623,7 +714,7 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     add_layer(net->pyr[l - 1][1], C, C, 8, C, identity(C, C), false, false);
   }
   const int d0 = desc->dec[0], d1 = desc->dec[1], d2 = desc->dec[2];
-  for (int l = 1; l <= L; ++l) {
+  for (int l = desc->finest; l <= L; ++l) {
     const int C = desc->ch[l - 1];
     // packed input order of c1: [F1 (C) | CV (ncv) | U (2) | zero pad];
     // source order of the blob: [CV (ncv) | F1 (C) | U (2)].
@@ -640,6 +731,31 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     add_layer(net->dec[l - 1][3], 2, d1 + d2, 8, d1 + d2, identity(d1 + d2, d1 + d2), true, false);
   }
 
+  // refinement: per layer the pointwise weights packed as the sepconv kernel
+  // reads them, then [b (np) | depthwise W (9 x cin_pad) | depthwise b]
+  std::vector<SepPacked> sep(desc->ref_layers);
+  {
+    int cin = d1 + d2 + 2;  // [h2 | h3 | flow], the order of the blob
+    for (int j = 0; j < desc->ref_layers; ++j) {
+      SepLayer& sl = net->ref[j];
+      const int cout = desc->ref_ch[j];
+      sl.bf16 = net->bf16act;
+      const int K = sl.bf16 ? 32 : 16;
+      sl.cin = cin;
+      sl.cin_pad = cdiv(cin, K) * K;
+      sl.cout = cout;
+      sl.np = cdiv(cout, 16) * 16;
+      sl.dil = desc->ref_dil[j];
+      const float* dw = src;
+      const float* dwb = src + (size_t)cin * 9;
+      const float* pw = dwb + cin;
+      const float* pb = pw + (size_t)cout * cin;
+      src = pb + cout;
+      pack_sep(sl, dw, dwb, pw, pb, sep[j]);
+      cin = cout;
+    }
+  }
+
   // one device allocation for every layer
   size_t total = 0;
   std::vector<size_t> offs;
@@ -648,6 +764,12 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     total = align_up(total + pk.w.size(), kAlign);
     offs.push_back(total);
     total = align_up(total + (pk.b.size() + pk.sc.size()) * sizeof(float), kAlign);
+  }
+  for (auto& sp : sep) {
+    offs.push_back(total);
+    total = align_up(total + sp.pw.size(), kAlign);
+    offs.push_back(total);
+    total = align_up(total + sp.rest.size() * sizeof(float), kAlign);
   }
   if (hipMalloc(&net->dmem, total) != hipSuccess) {
     delete net;
@@ -663,6 +785,17 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     slots[i]->w = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[2 * i]);
     slots[i]->b = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[2 * i + 1]);
     if (slots[i]->fp8) slots[i]->ws = slots[i]->b + packed[i].b.size();
+  }
+  for (size_t j = 0; j < sep.size(); ++j) {
+    const size_t o0 = offs[2 * packed.size() + 2 * j], o1 = offs[2 * packed.size() + 2 * j + 1];
+    memcpy(host.data() + o0, sep[j].pw.data(), sep[j].pw.size());
+    memcpy(host.data() + o1, sep[j].rest.data(), sep[j].rest.size() * sizeof(float));
+    SepLayer& sl = net->ref[j];
+    char* base = static_cast<char*>(net->dmem);
+    sl.pw = base + o0;
+    sl.b = reinterpret_cast<float*>(base + o1);
+    sl.dw = sl.b + sl.np;
+    sl.dwb = sl.dw + (size_t)9 * sl.cin_pad;
   }
   if (hipMemcpy(net->dmem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(net->dmem);

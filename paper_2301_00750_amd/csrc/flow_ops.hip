@@ -49,14 +49,19 @@ __global__ __launch_bounds__(256) void zero_u32_kernel(unsigned* p, size_t n) {
 
 // ---------------------------------------------------------------- up2
 
-// Source coordinate of output index i for 2x upsampling with half-pixel
-// centres: (i + 1/2) / 2 - 1/2 clamped to [0, n - 1]; exact in float.
-__device__ inline void up2_taps(int i, int n, int& i0, int& i1, float& f) {
-  float src = fmaxf((i + 0.5f) * 0.5f - 0.5f, 0.f);
+// Source coordinate of output index i for upsampling by a power of two s
+// with half-pixel centres: (i + 1/2) / s - 1/2 clamped to [0, n - 1]; exact
+// in float (inv_s = 1 / s).
+__device__ inline void up_taps(int i, int n, float inv_s, int& i0, int& i1, float& f) {
+  float src = fmaxf((i + 0.5f) * inv_s - 0.5f, 0.f);
   i0 = min((int)src, n - 1);
   f = src - (float)i0;
   if (i0 >= n - 1) f = 0.f;
   i1 = min(i0 + 1, n - 1);
+}
+
+__device__ inline void up2_taps(int i, int n, int& i0, int& i1, float& f) {
+  up_taps(i, n, 0.5f, i0, i1, f);
 }
 
 __global__ __launch_bounds__(256) void up2x2_kernel(const float* __restrict__ flow, int n, int h,
@@ -81,11 +86,13 @@ __global__ __launch_bounds__(256) void up2x2_kernel(const float* __restrict__ fl
   }
 }
 
-__global__ __launch_bounds__(256) void final_flow_kernel(const float* __restrict__ flow1, int n,
-                                                         int h1, int w1, float* __restrict__ out_a,
+__global__ __launch_bounds__(256) void final_flow_kernel(const float* __restrict__ flowf, int n,
+                                                         int hf, int wf, int scale,
+                                                         float* __restrict__ out_a,
                                                          float* __restrict__ out_b, int nsplit,
                                                          int H, int W, float* const* out_tab) {
   const size_t total = (size_t)n * H * W;
+  const float sc = (float)scale, inv_s = 1.f / (float)scale;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
        i += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(i % W);
@@ -93,12 +100,12 @@ __global__ __launch_bounds__(256) void final_flow_kernel(const float* __restrict
     const int img = (int)(i / ((size_t)W * H));
     int y0, y1, x0, x1;
     float fy, fx;
-    up2_taps(y, h1, y0, y1, fy);
-    up2_taps(x, w1, x0, x1, fx);
-    const float2* f = reinterpret_cast<const float2*>(flow1) + (size_t)img * h1 * w1;
-    const float2 a = f[y0 * w1 + x0], b = f[y0 * w1 + x1], c = f[y1 * w1 + x0], d = f[y1 * w1 + x1];
-    const float rx = 2.f * ((1.f - fy) * ((1.f - fx) * a.x + fx * b.x) + fy * ((1.f - fx) * c.x + fx * d.x));
-    const float ry = 2.f * ((1.f - fy) * ((1.f - fx) * a.y + fx * b.y) + fy * ((1.f - fx) * c.y + fx * d.y));
+    up_taps(y, hf, inv_s, y0, y1, fy);
+    up_taps(x, wf, inv_s, x0, x1, fx);
+    const float2* f = reinterpret_cast<const float2*>(flowf) + (size_t)img * hf * wf;
+    const float2 a = f[y0 * wf + x0], b = f[y0 * wf + x1], c = f[y1 * wf + x0], d = f[y1 * wf + x1];
+    const float rx = sc * ((1.f - fy) * ((1.f - fx) * a.x + fx * b.x) + fy * ((1.f - fx) * c.x + fx * d.x));
+    const float ry = sc * ((1.f - fy) * ((1.f - fx) * a.y + fx * b.y) + fy * ((1.f - fx) * c.y + fx * d.y));
     float* o = out_tab ? out_tab[img]
                : img < nsplit ? out_a + (size_t)img * 2 * H * W
                               : out_b + (size_t)(img - nsplit) * 2 * H * W;
@@ -316,12 +323,15 @@ hipError_t launch_up2x2(const float* flow, int n, int h, int w, float* U, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_final_flow(const float* flow1, int n, int h1, int w1, float* out_a, float* out_b,
-                             int nsplit, int H, int W, float* const* out_tab, hipStream_t s) {
+hipError_t launch_final_flow(const float* flow_f, int n, int hf, int wf, int scale, float* out_a,
+                             float* out_b, int nsplit, int H, int W, float* const* out_tab,
+                             hipStream_t s) {
   const size_t total = (size_t)n * H * W;
   if (!total) return hipSuccess;
-  final_flow_kernel<<<grid_for(total), 256, 0, s>>>(flow1, n, h1, w1, out_a, out_b, nsplit, H, W,
-                                                    out_tab);
+  if (scale < 2 || (scale & (scale - 1)) || (long)hf * scale < H || (long)wf * scale < W)
+    return hipErrorInvalidValue;
+  final_flow_kernel<<<grid_for(total), 256, 0, s>>>(flow_f, n, hf, wf, scale, out_a, out_b, nsplit,
+                                                    H, W, out_tab);
   return hipGetLastError();
 }
 

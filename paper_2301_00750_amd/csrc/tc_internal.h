@@ -143,11 +143,41 @@ CvPlan plan_cost_volume(int h, int w, int C);
 size_t cost_volume_partial_bytes(const CvPlan& p, int n, int h, int w);
 hipError_t launch_warp_cost_volume(const CvArgs& a, hipStream_t s);
 
-// Output: flow NCHW (n x 2 x H x W) = crop(2 * up2(flow1)); flow1 NHWC
-// (n x h1 x w1 x 2).  Images [0, nsplit) go to out_a, the rest to out_b.
-hipError_t launch_final_flow(const float* flow1, int n, int h1, int w1, float* out_a,
+// Output: flow NCHW (n x 2 x H x W) = crop(s * upsample(flow_f, s)) with
+// s = 2^finest (bilinear, half-pixel centres); flow_f NHWC (n x hf x wf x 2).
+// Images [0, nsplit) go to out_a, the rest to out_b.
+hipError_t launch_final_flow(const float* flow_f, int n, int hf, int wf, int scale, float* out_a,
                              float* out_b, int nsplit, int H, int W, float* const* out_tab,
                              hipStream_t s);
+
+// One depthwise separable layer of the refinement network: a depthwise 3x3
+// conv with dilation `dil` (zero padding), bias and LeakyReLU, then a
+// pointwise conv (bias, optional LeakyReLU).  The input channels are the
+// first `nblk` blocks of the blocked buffer `in` (T = float, or bfloat16 with
+// `bf16`), then, if `flow` is set, the two flow channels (NHWC float2) as one
+// more block.  Output: blocked activations, or (cout = 2, `add` set) the flow
+// add + result in NHWC float2.
+constexpr int kSepMaxC = 256;   // padded input channels
+struct SepLayer {
+  int cin, cin_pad, cout, np, dil;
+  int bf16;         // BF16 operands (chunks of 32 channels), else FP32 (16)
+  float* dw;        // device [9][cin_pad] depthwise weights (tap = 3 p + q), FP32
+  float* dwb;       // device [cin_pad]
+  void* pw;         // device, packed [cin_pad / chunk][np / 16][64 lanes][chunk / 4]
+  float* b;         // device [np]
+};
+struct SepArgs {
+  const void* in;
+  int in_cbt, nblk;
+  const float* flow;
+  int n, h, w;
+  float slope;
+  int lrelu;
+  void* out;
+  int out_cbt;
+  const float* add;
+};
+hipError_t launch_sepconv(const SepLayer& L, const SepArgs& a, hipStream_t s);
 
 // The paper's consistency step (Eq. 1-8).  Frames NCHW (n x 3 x h x w),
 // flows n x 2 x h x w: f_tp = flow from t to t-1, f_tn = flow from t to t+1.

@@ -28,7 +28,8 @@ EXPORTS = (
     "tc_fp8_e4m3_encode", "tc_decoder_list_workspace_bytes", "tc_flow_from_pyramid_list",
 )
 
-TC_OP_PYR_A, TC_OP_PYR_B, TC_OP_UP2, TC_OP_COST_VOLUME, TC_OP_C1, TC_OP_C2, TC_OP_C3, TC_OP_HEAD = range(8)
+(TC_OP_PYR_A, TC_OP_PYR_B, TC_OP_UP2, TC_OP_COST_VOLUME, TC_OP_C1, TC_OP_C2, TC_OP_C3, TC_OP_HEAD,
+ TC_OP_REFINE) = range(9)
 TC_STAGE_INPUT, TC_STAGE_OUTPUT, TC_STAGE_CONSISTENCY, TC_STAGE_PAPER = 1, 2, 3, 4
 
 
@@ -44,7 +45,9 @@ class TcError(RuntimeError):
 
 class NetDesc(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("ch", ctypes.c_int * 8), ("dec", ctypes.c_int * 3),
-                ("radius", ctypes.c_int), ("leaky", ctypes.c_float)]
+                ("radius", ctypes.c_int), ("leaky", ctypes.c_float), ("finest", ctypes.c_int),
+                ("ref_layers", ctypes.c_int), ("ref_ch", ctypes.c_int * 8),
+                ("ref_dil", ctypes.c_int * 8)]
 
     @classmethod
     def from_dict(cls, d):
@@ -56,6 +59,12 @@ class NetDesc(ctypes.Structure):
             s.dec[i] = c
         s.radius = d["radius"]
         s.leaky = d["leaky"]
+        s.finest = d.get("finest", 1)
+        ref = d.get("refine") or {}
+        s.ref_layers = len(ref.get("ch", []))
+        for i, (c, dl) in enumerate(zip(ref.get("ch", []), ref.get("dil", []))):
+            s.ref_ch[i] = c
+            s.ref_dil[i] = dl
         return s
 
 

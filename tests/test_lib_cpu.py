@@ -53,7 +53,7 @@ def tc():
     return tcflow
 
 
-@pytest.mark.parametrize("name", ["tiny", "fullhd"])
+@pytest.mark.parametrize("name", ["tiny", "fullhd", "tiny_sepref", "fullhd_sepref"])
 def test_weight_floats_matches_generator(tc, name):
     d = synth.load_desc(name)
     cd = tc.NetDesc.from_dict(d)
@@ -126,3 +126,16 @@ def test_fp8_encoder_matches_torch_e4m3fn(tc):
     o2 = np.empty(3, np.uint8)
     tc.lib().tc_fp8_e4m3_encode(big.ctypes.data, o2.ctypes.data, 3)
     assert list(o2) == [0x7e, 0x7e, 0xfe]
+
+
+@pytest.mark.parametrize("change", [
+    dict(finest=0), dict(finest=5),
+    dict(refine={"ch": [48, 4], "dil": [1, 1]}),          # last layer must output 2
+    dict(refine={"ch": [12, 2], "dil": [1, 1]}),          # widths are multiples of 8
+    dict(refine={"ch": [48, 2], "dil": [0, 1]}),          # dilation >= 1
+    dict(refine={"ch": [48, 2], "dil": [1, 65]}),
+])
+def test_bad_variant_descriptors(tc, change):
+    d = dict(synth.load_desc("tiny_sepref"), **change)
+    cd = tc.NetDesc.from_dict(d)
+    assert tc.lib().tc_weight_floats(ctypes.byref(cd)) == 0
