@@ -63,6 +63,22 @@ def c1_flops(desc, h, w, level=1, images=2):
     return 2.0 * px * 9 * din * desc["dec"][0]
 
 
+def refine_flops(desc, h, w, images=2):
+    """Algorithmic FLOPs of the refinement layers of one decoder pass (fw + bw):
+    per layer 2 (9 c_in + c_in c_out) per pixel of the finest estimator level."""
+    ref = desc.get("refine") or {}
+    if not ref.get("ch"):
+        return 0.0
+    m = 2 ** desc["levels"]
+    f = desc.get("finest", 1)
+    px = images * ((-(-h // m) * m) >> f) * ((-(-w // m) * m) >> f)
+    cin, fl = desc["dec"][1] + desc["dec"][2] + 2, 0.0
+    for co in ref["ch"]:
+        fl += 2.0 * px * (9 * cin + cin * co)
+        cin = co
+    return fl
+
+
 def frame_lower_bound_ms(desc, h, w, peak_tflops, bpe=4):
     """Sum over the unfused layer graph of max(FLOP / peak, bytes / HBM),
     bytes = each layer's input read once + output written once."""
@@ -82,7 +98,7 @@ def frame_lower_bound_ms(desc, h, w, peak_tflops, bpe=4):
         t += layer(prev_px, prev_c, px, ch[l - 1], 2.0 * px * 9 * prev_c * ch[l - 1])
         t += layer(px, ch[l - 1], px, ch[l - 1], 2.0 * px * 9 * ch[l - 1] * ch[l - 1])
         prev_px, prev_c = px, ch[l - 1]
-    for l in range(1, L + 1):
+    for l in range(desc.get("finest", 1), L + 1):
         px = 2 * (hp >> l) * (wp >> l)  # fw + bw
         C = ch[l - 1]
         # warp + cost volume: read F1, F2 (+U), write 81 ch
@@ -92,6 +108,14 @@ def frame_lower_bound_ms(desc, h, w, peak_tflops, bpe=4):
         t += layer(px, dec[0], px, dec[1], 2.0 * px * 9 * dec[0] * dec[1])
         t += layer(px, dec[1], px, dec[2], 2.0 * px * 9 * dec[1] * dec[2])
         t += layer(px, dec[1] + dec[2], px, 2, 2.0 * px * 9 * (dec[1] + dec[2]) * 2)
+    ref = desc.get("refine") or {}
+    if ref.get("ch"):
+        f = desc.get("finest", 1)
+        px = 2 * (hp >> f) * (wp >> f)
+        cin = dec[1] + dec[2] + 2
+        for co in ref["ch"]:
+            t += layer(px, cin, px, co, 2.0 * px * (9 * cin + cin * co))
+            cin = co
     t += 52.0 * h * w / (PEAK_HBM * 1e9)  # consistency
     return t * 1e3
 
@@ -107,9 +131,10 @@ def blas_threads():
     return os.cpu_count()
 
 
-def measure(tcflow, desc, blob, precision, I, P, K, W, frames):
+def measure(tcflow, desc, blob, precision, I, P, K, W, frames, probe_stage=None):
     """Throughput run (K timed steps after W warm-up steps) and latency run of
-    the streaming path at one precision.  Returns a dict of results."""
+    the streaming path at one precision.  Returns a dict of results; c1_* are
+    the probed stage's launches (default: the level-1 decoder conv1)."""
     H, W_ = desc["height"], desc["width"]
     net = tcflow.Net(desc, blob, precision=precision)
     st = tcflow.StreamState(net, 1, H, W_, device=I[0].device)
@@ -124,7 +149,8 @@ def measure(tcflow, desc, blob, precision, I, P, K, W, frames):
 
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    probe_stage = tcflow.stage_id(1, tcflow.TC_OP_C1)
+    if probe_stage is None:
+        probe_stage = tcflow.stage_id(1, tcflow.TC_OP_C1)
     probe = tcflow.Probe(probe_stage, K)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -168,6 +194,9 @@ def main():
                     help="1080p frames of the paper's full consistency step to time (0 = skip)")
     ap.add_argument("--serve-frames", type=int, default=90,
                     help="frames per stream of the 16-stream serving mix (0 = skip)")
+    ap.add_argument("--variants", default="fullhd_sepref",
+                    help="comma-separated network variants (configs) measured in every precision "
+                         "form after the base network ('' = none)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="before timing, run 3 plain device copies of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -279,6 +308,14 @@ def main():
     if forms:
         result["precision_forms"] = forms
 
+    variants = {}
+    for vname in [v for v in args.variants.split(",") if v]:
+        vd = synth.load_desc(vname)
+        variants[vname] = variant_leg(tcflow, vd, I, P, K, args.warmup, args.frames,
+                                      ["fp32"] + [f for f in args.forms.split(",") if f], r["fps"])
+    if variants:
+        result["variants"] = {k: v["report"] for k, v in variants.items()}
+
     if args.paper_steps > 0:
         result["paper_consistency"] = paper_leg(tcflow, nets["fp32"], I, P, args.paper_steps,
                                                 r["ms"])
@@ -291,7 +328,48 @@ def main():
         result["epe_vs_oracle"] = epe.pop("fp32")
         for form, e in epe.items():
             result["precision_forms"][form]["epe_vs_oracle"] = e
+        for vname, v in variants.items():
+            _, vepe = cpu_leg(v["nets"], v["desc"], I, P, 1)
+            for form, e in vepe.items():
+                result["variants"][vname][form]["epe_vs_oracle"] = e
     print(json.dumps(result), flush=True)
+
+
+def variant_leg(tcflow, vdesc, I, P, K, W, frames, forms, base_fps):
+    """The streaming path with a network variant (finest estimator dropped,
+    separable refinement) in each precision form; the probe times the
+    refinement layers of each decoder pass."""
+    H, W_ = vdesc["height"], vdesc["width"]
+    blob = synth.he_weights(vdesc)
+    f = vdesc.get("finest", 1)
+    has_ref = bool((vdesc.get("refine") or {}).get("ch"))
+    stage = tcflow.stage_id(f, tcflow.TC_OP_REFINE if has_ref else tcflow.TC_OP_C1)
+    precs = {"fp32": tcflow.TC_FP32, "bf16": tcflow.TC_BF16, "fp8": tcflow.TC_FP8_E4M3}
+    report, nets = {"finest": f, "refine": vdesc.get("refine")}, {}
+    for form in forms:
+        log(f"variant {vdesc['name']} {form}: timing {K} steps")
+        rv = measure(tcflow, vdesc, blob, precs[form], I, P, K, W, frames, probe_stage=stage)
+        log(f"variant {vdesc['name']} {form}: {rv['fps']:.1f} frames/s")
+        nets[form] = rv["net"]
+        mpeak = PEAK_FP32_MFMA if form == "fp32" else PEAK_BF16_MFMA
+        t_star = frame_lower_bound_ms(vdesc, H, W_, mpeak if form != "fp8" else PEAK_FP8_MFMA,
+                                      bpe=4 if form == "fp32" else 2)
+        e = {"value": round(rv["fps"], 2), "unit": "frames/s", "ms_per_step": round(rv["ms"], 4),
+             "speedup_vs_base_fp32": round(rv["fps"] / base_fps, 3),
+             "p50_frame_ms": round(float(np.percentile(rv["lat"], 50)), 4),
+             "p99_frame_ms": round(float(np.percentile(rv["lat"], 99)), 4),
+             "frame_roofline": {"t_star_ms": round(t_star, 4), "frac": round(t_star / rv["ms"], 4)}}
+        if has_ref:
+            rf = refine_flops(vdesc, H, W_)
+            ach = rf / (rv["c1_alone_ms"] * 1e-3) / 1e12
+            e["refinement"] = {"kernel": "sepconv_mfma (all layers, fw+bw batch)",
+                               "gflop_per_pass": round(rf / 1e9, 3),
+                               "avg_ms": round(rv["c1_ms"], 5),
+                               "alone_avg_ms": round(rv["c1_alone_ms"], 5),
+                               "alone_achieved_tflops": round(ach, 2), "peak_tflops": mpeak,
+                               "alone_frac": round(ach / mpeak, 4)}
+        report[form] = e
+    return {"report": report, "nets": nets, "desc": vdesc}
 
 
 def serve_leg(tcflow, desc, blob, nframes, unique=6):

@@ -11,17 +11,16 @@ typedef unsigned short bf16;  // storage type of bfloat16 activations
 
 __device__ inline float bf2f(bf16 h) { return __uint_as_float((unsigned)h << 16); }
 
-// float -> bfloat16, round to nearest even on the bit pattern; NaN stays NaN.
-__device__ inline bf16 f2bf(float f) {
-  unsigned u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (bf16)(u >> 16);
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+// float -> bfloat16 with the hardware conversion (v_cvt_pk_bf16_f32: round to
+// nearest even; NaN stays NaN).
+__device__ inline unsigned pack2(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(float2v{a, b}, bf16x2));
 }
 
-__device__ inline unsigned pack2(float a, float b) {
-  return (unsigned)f2bf(a) | ((unsigned)f2bf(b) << 16);
-}
+__device__ inline bf16 f2bf(float f) { return (bf16)(pack2(f, 0.f) & 0xffffu); }
 
 __device__ inline void load8(const float* p, float (&v)[8]) {
   const f4 a = reinterpret_cast<const f4*>(p)[0], b = reinterpret_cast<const f4*>(p)[1];

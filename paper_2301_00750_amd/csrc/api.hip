@@ -179,7 +179,8 @@ DecLayout dec_layout(const tc_net* net, int nb, int h, int w) {
   L.U = take(px * 2 * sizeof(float));
   L.Z = take(px * net->zcb * 8 * net->esz);
   L.H1 = take(px * net->d.dec[0] * net->esz);
-  L.H23 = take(px * (net->d.dec[1] + net->d.dec[2]) * net->esz);
+  // h2 | h3 (| the flow as one more block, the refinement's input)
+  L.H23 = take(px * (net->d.dec[1] + net->d.dec[2] + (net->d.ref_layers ? 8 : 0)) * net->esz);
   int rw = 0;  // widest refinement activation (the last layer writes a flow)
   for (int j = 0; j + 1 < net->d.ref_layers; ++j) rw = std::max(rw, net->d.ref_ch[j]);
   L.R[0] = take(px * rw * net->esz);
@@ -489,6 +490,7 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
   if (dslots) TC_TRY_HIP(launch_zero_u32(dslots, (size_t)3 * d.levels * nb * kSub, s));
   const AmaxIn none{nullptr, nullptr, 0};
   const int d0b = d.dec[0] / 8, d1b = d.dec[1] / 8, d23b = (d.dec[1] + d.dec[2]) / 8;
+  const int hcb = d23b + (d.ref_layers ? 1 : 0);  // blocks per image of H23
   int cur = 0;
   const int fl = d.finest;
   for (int l = d.levels; l >= fl; --l) {
@@ -541,16 +543,16 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
                         hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C1), part, net->bf16act,
                         ain_c1, L[1].fp8 ? dslot(l, 1) : nullptr, s);
     if (st) return st;
-    st = conv_layer(L[1], plain_view(H1, d0b), d0b, plain_view(H1, d0b), hl, wl, H23, d23b, 0, 0,
+    st = conv_layer(L[1], plain_view(H1, d0b), d0b, plain_view(H1, d0b), hl, wl, H23, hcb, 0, 0,
                     nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C2), part, net->bf16act,
                     ain_c2, L[2].fp8 ? dslot(l, 2) : nullptr, s);
     if (st) return st;
-    st = conv_layer(L[2], plain_view(H23, d23b), d1b, plain_view(H23, d23b), hl, wl, H23, d23b,
+    st = conv_layer(L[2], plain_view(H23, hcb), d1b, plain_view(H23, hcb), hl, wl, H23, hcb,
                     d1b, 0, nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C3), part, net->bf16act,
                     ain_c3, nullptr, s);
     if (st) return st;
     const int nxt = cur ^ 1;
-    st = conv_layer(L[3], plain_view(H23, d23b), d23b, plain_view(H23, d23b), hl, wl, flows[nxt],
+    st = conv_layer(L[3], plain_view(H23, hcb), d23b, plain_view(H23, hcb), hl, wl, flows[nxt],
                     0, 0, 1, Ul, hl, wl, 0, 0.f, nb, 1, TC_STAGE(l, TC_OP_HEAD), part, net->bf16act,
                     nullptr, nullptr, s);
     if (st) return st;
@@ -558,17 +560,18 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
   }
   if (d.ref_layers > 0) {
     // refinement on [h2 | h3 | flow_f] (H23 still holds the finest level's
-    // h2 and h3); the last layer writes flow_f + increment
+    // h2 and h3, the flow goes into its last block); the last layer writes
+    // flow_f + increment
     const int hl = g.h[fl], wl = g.w[fl];
     char* R[2] = {ws + D.R[0], ws + D.R[1]};
     probe_begin(TC_STAGE(fl, TC_OP_REFINE), s);
+    TC_TRY_HIP(launch_flow_to_block(flows[cur], nb, hl * wl, H23, hcb, d23b, net->bf16act, s));
     for (int j = 0; j < d.ref_layers; ++j) {
       const bool last = j == d.ref_layers - 1;
       SepArgs a;
       a.in = j == 0 ? static_cast<const void*>(H23) : R[(j - 1) & 1];
-      a.in_cbt = j == 0 ? d23b : d.ref_ch[j - 1] / 8;
+      a.in_cbt = j == 0 ? hcb : d.ref_ch[j - 1] / 8;
       a.nblk = a.in_cbt;
-      a.flow = j == 0 ? flows[cur] : nullptr;
       a.n = nb;
       a.h = hl;
       a.w = wl;

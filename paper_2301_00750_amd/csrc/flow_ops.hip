@@ -114,6 +114,20 @@ __global__ __launch_bounds__(256) void final_flow_kernel(const float* __restrict
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void flow_to_block_kernel(const float* __restrict__ flow, int n,
+                                                            int hw, T* __restrict__ out, int cbt,
+                                                            int cb) {
+  const size_t total = (size_t)n * hw;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t img = i / hw, p = i - img * hw;
+    const float2 f = reinterpret_cast<const float2*>(flow)[i];
+    const float v[8] = {f.x, f.y, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    store8(out + ((img * cbt + cb) * hw + p) * 8, v);
+  }
+}
+
 // ---------------------------------------------------------------- warp + cost volume
 //
 // A workgroup owns a TY x TX tile of pixels (one per thread).  Per chunk of 8
@@ -332,6 +346,19 @@ hipError_t launch_final_flow(const float* flow_f, int n, int hf, int wf, int sca
     return hipErrorInvalidValue;
   final_flow_kernel<<<grid_for(total), 256, 0, s>>>(flow_f, n, hf, wf, scale, out_a, out_b, nsplit,
                                                     H, W, out_tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_flow_to_block(const float* flow, int n, int hw, void* out, int cbt, int cb,
+                                int as_bf16, hipStream_t s) {
+  const size_t total = (size_t)n * hw;
+  if (!total) return hipSuccess;
+  if (as_bf16)
+    flow_to_block_kernel<bf16><<<grid_for(total), 256, 0, s>>>(flow, n, hw,
+                                                               static_cast<bf16*>(out), cbt, cb);
+  else
+    flow_to_block_kernel<float><<<grid_for(total), 256, 0, s>>>(flow, n, hw,
+                                                                static_cast<float*>(out), cbt, cb);
   return hipGetLastError();
 }
 

@@ -154,10 +154,11 @@ hipError_t launch_final_flow(const float* flow_f, int n, int hf, int wf, int sca
 // conv with dilation `dil` (zero padding), bias and LeakyReLU, then a
 // pointwise conv (bias, optional LeakyReLU).  The input channels are the
 // first `nblk` blocks of the blocked buffer `in` (T = float, or bfloat16 with
-// `bf16`), then, if `flow` is set, the two flow channels (NHWC float2) as one
-// more block.  Output: blocked activations, or (cout = 2, `add` set) the flow
-// add + result in NHWC float2.
-constexpr int kSepMaxC = 256;   // padded input channels
+// `bf16`); channels beyond them up to cin_pad have zero weights.  Output:
+// blocked activations, or (cout = 2, `add` set) the flow add + result in
+// NHWC float2.
+constexpr int kSepMaxC = 256;          // padded input channels
+constexpr int kSepPwFloats = 16384;    // pointwise weights held in LDS (64 KiB)
 struct SepLayer {
   int cin, cin_pad, cout, np, dil;
   int bf16;         // BF16 operands (chunks of 32 channels), else FP32 (16)
@@ -169,7 +170,6 @@ struct SepLayer {
 struct SepArgs {
   const void* in;
   int in_cbt, nblk;
-  const float* flow;
   int n, h, w;
   float slope;
   int lrelu;
@@ -178,6 +178,12 @@ struct SepArgs {
   const float* add;
 };
 hipError_t launch_sepconv(const SepLayer& L, const SepArgs& a, hipStream_t s);
+
+// Writes the flow (NHWC float2) as channel block `cb` of a blocked buffer with
+// `cbt` blocks per image (channels 0, 1 = the flow, 2..7 = 0), float or
+// bfloat16.
+hipError_t launch_flow_to_block(const float* flow, int n, int hw, void* out, int cbt, int cb,
+                                int as_bf16, hipStream_t s);
 
 // The paper's consistency step (Eq. 1-8).  Frames NCHW (n x 3 x h x w),
 // flows n x 2 x h x w: f_tp = flow from t to t-1, f_tn = flow from t to t+1.
