@@ -209,6 +209,53 @@ TC_API int tc_consistency_paper(const float* I_prev, const float* I, const float
 
 /* ---- measurement probe -------------------------------------------------- */
 
+/* ---- training of a student network on teacher flows --------------------
+ *
+ * Paper Sec. 3.2 ("Training") and the supplementary loss: the loss is a sum
+ * over the flow estimators, weighted equally, of the robust loss of Eq. S2,
+ * mean over the level's pixels of (|du| + |dv| + loss_eps)^loss_q, against
+ * the teacher flow edge-padded to the network's grid, averaged over each
+ * 2^l x 2^l block and divided by 2^l (level-l pixels).  The optimizer is
+ * AdamW (decoupled weight decay): p <- p (1 - lr weight_decay), then the
+ * bias-corrected Adam update with beta1, beta2, eps.  Everything is FP32;
+ * weights, gradients and the two Adam moments are kept in the layout of the
+ * weight blob (tc_weight_floats). */
+typedef struct {
+  float lr, beta1, beta2, eps, weight_decay;
+  float loss_eps, loss_q;
+} tc_train_params;
+typedef struct tc_trainer tc_trainer; /* opaque */
+
+/* lr 1e-4, beta1 0.9, beta2 0.99, eps 1e-8, weight_decay 4e-4, loss_eps
+ * 0.01, loss_q 0.4. */
+TC_API void tc_train_default_params(tc_train_params* p);
+
+/* Trainer for batches of up to max_n frame pairs of h x w (any size; padded
+ * to a multiple of 2^L like the inference path).  The network must have an
+ * estimator at every level, no refinement, and ch[l] + 88 <= 128.  Copies
+ * `host_weights` (the blob) as the initial weights; allocates all its device
+ * memory here (nothing is allocated per step).  TC_ERR_SHAPE for an
+ * unsupported descriptor or a wrong weight count. */
+TC_API int tc_trainer_create(const tc_net_desc* desc, const float* host_weights, size_t n_floats,
+                             const tc_train_params* params, int max_n, int h, int w,
+                             tc_trainer** out);
+TC_API void tc_trainer_destroy(tc_trainer* t);
+
+/* Loss and gradient for n pairs: frames A (flow source) and B (n x 3 x h x
+ * w, device), teacher flows A -> B (n x 2 x h x w, device, input pixels).
+ * The gradient stays in the trainer; the loss (one float) is written to
+ * device memory `loss_out` if not NULL.  Asynchronous on `stream`. */
+TC_API int tc_trainer_grad(tc_trainer* t, const float* A, const float* B, const float* teacher,
+                           int n, float* loss_out, void* stream);
+/* tc_trainer_grad followed by one AdamW step. */
+TC_API int tc_trainer_step(tc_trainer* t, const float* A, const float* B, const float* teacher,
+                           int n, float* loss_out, void* stream);
+/* Copies weights (which = 0), gradient (1), first (2) or second moment (3),
+ * n_floats values in blob layout, to `dst` (host or device). */
+TC_API int tc_trainer_copy(const tc_trainer* t, int which, float* dst, void* stream);
+/* Number of AdamW steps taken. */
+TC_API int tc_trainer_steps_done(const tc_trainer* t);
+
 /* Stage ids: TC_STAGE(level, op) for the per-level ops, plus three
  * whole-frame stages. */
 #define TC_STAGE(level, op) ((level) * 16 + (op))

@@ -26,6 +26,8 @@ EXPORTS = (
     "tc_consistency_step", "tc_probe_enable", "tc_probe_read", "tc_probe_disable",
     "tc_paper_default_params", "tc_paper_workspace_bytes", "tc_consistency_paper",
     "tc_fp8_e4m3_encode", "tc_decoder_list_workspace_bytes", "tc_flow_from_pyramid_list",
+    "tc_train_default_params", "tc_trainer_create", "tc_trainer_destroy", "tc_trainer_grad",
+    "tc_trainer_step", "tc_trainer_copy", "tc_trainer_steps_done",
 )
 
 (TC_OP_PYR_A, TC_OP_PYR_B, TC_OP_UP2, TC_OP_COST_VOLUME, TC_OP_C1, TC_OP_C2, TC_OP_C3, TC_OP_HEAD,
@@ -75,6 +77,13 @@ class PaperParams(ctypes.Structure):
                 ("iterations", ctypes.c_int)]
 
 
+class TrainParams(ctypes.Structure):
+    """tc_train_params: lr, beta1, beta2, eps, weight_decay, loss_eps, loss_q."""
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float),
+                ("loss_eps", ctypes.c_float), ("loss_q", ctypes.c_float)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
@@ -105,6 +114,14 @@ def _load():
                                            ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp]),
         "tc_consistency_paper": (ci, [vp] * 9 + [ctypes.POINTER(PaperParams), ci, ci, ci, vp, vp,
                                                  sz, vp]),
+        "tc_train_default_params": (None, [ctypes.POINTER(TrainParams)]),
+        "tc_trainer_create": (ci, [ctypes.POINTER(NetDesc), vp, sz, ctypes.POINTER(TrainParams), ci,
+                                   ci, ci, ctypes.POINTER(vp)]),
+        "tc_trainer_destroy": (None, [vp]),
+        "tc_trainer_grad": (ci, [vp, vp, vp, vp, ci, vp, vp]),
+        "tc_trainer_step": (ci, [vp, vp, vp, vp, ci, vp, vp]),
+        "tc_trainer_copy": (ci, [vp, ci, vp, vp]),
+        "tc_trainer_steps_done": (ci, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -428,3 +445,72 @@ class StreamState:
         """(flow_fw, flow_bw) of the last pushed frame (after synchronising)."""
         lane = (self.t - 1) % self.nd
         return self.fw[lane], self.bw[lane]
+
+
+def train_params(**kw):
+    """tc_train_default_params with fields overridden by keyword."""
+    p = TrainParams()
+    _lib.tc_train_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class Trainer:
+    """tc_trainer: FP32 training of a network on teacher flows (AdamW)."""
+
+    def __init__(self, desc: dict, weights, max_n: int, h: int, w: int, params=None):
+        self.desc = dict(desc)
+        self._cdesc = NetDesc.from_dict(desc)
+        self._prm = params if params is not None else train_params()
+        wb = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+        self.n_floats = wb.size
+        self.h, self.w, self.max_n = h, w, max_n
+        hdl = ctypes.c_void_p()
+        _check("tc_trainer_create", _lib.tc_trainer_create(
+            ctypes.byref(self._cdesc), wb.ctypes.data, wb.size, ctypes.byref(self._prm), max_n, h,
+            w, ctypes.byref(hdl)))
+        self._h = hdl
+        self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.tc_trainer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _args(self, A, B, T):
+        _frames(A, "A", 3)
+        _frames(B, "B", 3)
+        _frames(T, "teacher", 2)
+        if A.shape != B.shape or A.shape[2:] != (self.h, self.w) or T.shape[0] != A.shape[0] \
+                or T.shape[2:] != A.shape[2:]:
+            raise ValueError("frames and teacher flows must be n x {3,2} x h x w of the trainer")
+        return A.shape[0]
+
+    def grad(self, A, B, T, stream=None):
+        n = self._args(A, B, T)
+        _check("tc_trainer_grad", _lib.tc_trainer_grad(self._h, _ptr(A), _ptr(B), _ptr(T), n,
+                                                       _ptr(self.loss), _stream(stream)))
+        return self.loss
+
+    def step(self, A, B, T, stream=None):
+        n = self._args(A, B, T)
+        _check("tc_trainer_step", _lib.tc_trainer_step(self._h, _ptr(A), _ptr(B), _ptr(T), n,
+                                                       _ptr(self.loss), _stream(stream)))
+        return self.loss
+
+    def copy(self, which: int = 0):
+        """Weights (0), gradient (1), Adam moments (2, 3) as a float32 cuda tensor."""
+        out = torch.empty(self.n_floats, dtype=torch.float32, device="cuda")
+        _check("tc_trainer_copy", _lib.tc_trainer_copy(self._h, which, _ptr(out), _stream()))
+        return out
+
+    @property
+    def steps_done(self):
+        return _lib.tc_trainer_steps_done(self._h)

@@ -1,0 +1,107 @@
+"""GPU parity of student training (tc_trainer_*) against the FP64 oracle.
+
+* loss and full gradient of one batch vs the oracle's float64 autograd
+  gradient (which is itself pinned to finite differences): every layer's
+  gradient within 1e-3 of that layer's largest entry, the whole gradient
+  within 1e-4 relative L2 (FP32 sums over at most a few thousand pixels per
+  weight);
+* AdamW steps vs the oracle's AdamW fed with the GPU's gradients;
+* a few steps on a fixed batch lower the loss.
+Frames 21 x 30 pad to 24 x 32 (3 levels): the padding path is covered.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import student_oracle as S
+from oracle import tcflow_oracle as O
+from paper_2301_00750_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tc():
+    from paper_2301_00750_amd import tcflow
+    assert torch.cuda.is_available()
+    return tcflow
+
+
+def batch(n, h, w, seed):
+    sc = [synth.LayeredScene(w, h, seed=seed + i, max_shift=2.0) for i in range(n)]
+    A = torch.stack([s.frame(0) for s in sc])
+    B = torch.stack([s.frame(1) for s in sc])
+    T = torch.stack([s.gt_flow(0, 1)[0] for s in sc])
+    return A, B, T
+
+
+def layer_slices(d, blob):
+    wts = O.unpack_weights(blob, d)
+    pos, out = 0, []
+    for name, (w, b) in wts.items():
+        out.append((name, pos, pos + w.size + b.size))
+        pos += w.size + b.size
+    return out
+
+
+def test_gradient_vs_oracle(tc):
+    d = synth.load_desc("student")
+    blob = synth.he_weights(d)
+    A, B, T = batch(2, 21, 30, 5)
+    say("[train] gradient 2 x 21x30")
+    tr = tc.Trainer(d, blob, 2, 21, 30)
+    loss = tr.grad(A.cuda().contiguous(), B.cuda().contiguous(), T.cuda().contiguous())
+    g = tr.copy(1).cpu().double().numpy()
+    lref, gref = S.loss_and_grad(blob.astype(np.float64), A.double(), B.double(), T.double(), d)
+    say(f"   loss gpu={float(loss):.7f} oracle={lref:.7f}")
+    assert abs(float(loss) - lref) <= 1e-5 * abs(lref)
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    say(f"   gradient relative L2 error {rel:.2e}")
+    worst = []
+    for name, a, b in layer_slices(d, blob):
+        err = np.abs(g[a:b] - gref[a:b]).max() / max(np.abs(gref[a:b]).max(), 1e-12)
+        worst.append((err, name))
+    worst.sort(reverse=True)
+    say(f"   worst layers: {worst[:4]}")
+    assert rel <= 1e-4
+    assert worst[0][0] <= 1e-3
+
+
+def test_adamw_steps_vs_oracle(tc):
+    d = synth.load_desc("student")
+    blob = synth.he_weights(d)
+    A, B, T = (x.cuda().contiguous() for x in batch(2, 24, 32, 9))
+    prm = dict(S.TRAIN_DEFAULTS, lr=1e-3)
+    tr = tc.Trainer(d, blob, 2, 24, 32, params=tc.train_params(lr=1e-3))
+    p, m, v = blob.astype(np.float64), np.zeros(blob.size), np.zeros(blob.size)
+    say("[train] three AdamW steps")
+    for t in range(1, 4):
+        tr.grad(A, B, T)
+        g = tr.copy(1).cpu().double().numpy()
+        tr.step(A, B, T)        # recomputes the same gradient, then updates
+        p, m, v = S.adamw_step(p, g, m, v, t, prm)
+        got = tr.copy(0).cpu().double().numpy()
+        err = np.abs(got - p).max()
+        say(f"   step {t}: max |w_gpu - w_oracle| = {err:.2e}")
+        assert err <= 2e-6
+    assert tr.steps_done == 3
+
+
+def test_training_lowers_loss(tc):
+    d = synth.load_desc("student")
+    A, B, T = (x.cuda().contiguous() for x in batch(4, 64, 96, 13))
+    tr = tc.Trainer(d, synth.he_weights(d), 4, 64, 96, params=tc.train_params(lr=2e-3))
+    say("[train] 40 steps on one batch")
+    first = float(tr.grad(A, B, T))
+    for _ in range(40):
+        tr.step(A, B, T)
+    last = float(tr.grad(A, B, T))
+    say(f"   loss {first:.4f} -> {last:.4f}")
+    assert np.isfinite(last) and last < 0.9 * first
