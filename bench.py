@@ -197,6 +197,8 @@ def main():
     ap.add_argument("--variants", default="fullhd_sepref",
                     help="comma-separated network variants (configs) measured in every precision "
                          "form after the base network ('' = none)")
+    ap.add_argument("--student", type=int, default=1,
+                    help="measure the distilled student (weights/student.npy) at 1080p and 4K")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="before timing, run 3 plain device copies of this many MiB (a known-size "
                          "reference for hardware byte counters)")
@@ -316,6 +318,9 @@ def main():
     if variants:
         result["variants"] = {k: v["report"] for k, v in variants.items()}
 
+    if args.student:
+        result["student"] = student_leg(tcflow, nets, I, P, K, args.warmup, args.frames, r["fps"])
+
     if args.paper_steps > 0:
         result["paper_consistency"] = paper_leg(tcflow, nets["fp32"], I, P, args.paper_steps,
                                                 r["ms"])
@@ -370,6 +375,100 @@ def variant_leg(tcflow, vdesc, I, P, K, W, frames, forms, base_fps):
                                "alone_frac": round(ach / mpeak, 4)}
         report[form] = e
     return {"report": report, "nets": nets, "desc": vdesc}
+
+
+def student_leg(tcflow, nets, I, P, K, W, frames, base_fps):
+    """The distilled student (3 levels, half width, trained with the
+    library's trainer on the teacher's flows): BF16 streaming at 1920x1080
+    and 3840x2160, EPE against the FP32 teacher, the forward-backward
+    agreement fallback to the teacher, and the training step rate."""
+    from paper_2301_00750_amd import student as stu
+    path = stu.DEFAULT_WEIGHTS
+    if not os.path.exists(path):
+        return {"status": "no trained weights (python -m paper_2301_00750_amd.student)"}
+    wts = np.load(path, allow_pickle=False)
+    meta_path = os.path.splitext(path)[0] + ".json"
+    meta = json.load(open(meta_path)) if os.path.exists(meta_path) else {}
+    sd = synth.load_desc("student")
+    td = synth.load_desc("fullhd")
+    H, W_ = td["height"], td["width"]
+    out = {"config": {"levels": sd["levels"], "channels": sd["ch"], "decoder": sd["dec"],
+                      "trained_steps": meta.get("steps"), "train_pairs": meta.get("pairs"),
+                      "train_batch": meta.get("batch"), "train_resolution": meta.get("resolution"),
+                      "final_loss": (meta.get("loss_history") or [[None, None]])[-1][1],
+                      "train_ms_per_step_logged": meta.get("step_ms")}}
+    # streaming, student BF16, 1080p
+    d1080 = dict(sd, height=H, width=W_)
+    log(f"student bf16 1080p: timing {K} steps")
+    rs = measure(tcflow, d1080, wts, tcflow.TC_BF16, I, P, K, W, frames)
+    out["bf16_1080p"] = {"value": round(rs["fps"], 2), "unit": "frames/s",
+                         "speedup_vs_teacher_fp32": round(rs["fps"] / base_fps, 3),
+                         "p99_frame_ms": round(float(np.percentile(rs["lat"], 99)), 4)}
+    s_bf16 = rs["net"]
+    s_fp32 = tcflow.Net(sd, wts)
+    teacher = nets["fp32"]
+    teacher_fast = nets.get("bf16", teacher)
+    # EPE against the FP32 teacher and the agreement fallback, frame by frame
+    fb = stu.FallbackFlow(s_bf16, teacher_fast, H, W_, threshold=0.9)
+    epe_s, epe_s32, epe_out, agrees = [], [], [], []
+    nf = min(12, len(I) - 1)
+    for t in range(1, nf + 1):
+        tf, tb = teacher.flow_estimate_pair(I[t - 1], I[t])
+        sf, sb = s_fp32.flow_estimate_pair(I[t - 1], I[t])
+        f, b, agree = fb(I[t - 1], I[t])
+        bf, bb = s_bf16.flow_estimate_pair(I[t - 1], I[t])
+        for x, y, acc in ((bf, tf, epe_s), (bb, tb, epe_s), (sf, tf, epe_s32), (sb, tb, epe_s32),
+                          (f, tf, epe_out), (b, tb, epe_out)):
+            acc.append(float(torch.sqrt(((x - y) ** 2).sum(1)).mean()))
+        agrees.append(agree)
+    out["epe_vs_teacher_px"] = {"student_bf16": round(float(np.mean(epe_s)), 4),
+                                "student_fp32": round(float(np.mean(epe_s32)), 4),
+                                "with_fallback": round(float(np.mean(epe_out)), 4),
+                                "frames": nf}
+    out["fallback"] = {"threshold": 0.9, "rate": round(fb.fallbacks / max(1, fb.frames), 4),
+                       "mean_agreement": round(float(np.mean(agrees)), 4)}
+    # with the per-frame agreement check (host decision) in the loop
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    prev_out = P[0]
+    torch.cuda.synchronize()
+    n_chk = min(60, len(I) - 1)
+    ev0.record()
+    for t in range(1, n_chk + 1):
+        f, b, _ = fb(I[t - 1], I[t])
+        prev_out = tcflow.consistency_step(P[t], prev_out, f, b, 0.5)
+    ev1.record()
+    torch.cuda.synchronize()
+    out["bf16_1080p_with_fallback_check"] = {
+        "value": round(n_chk / (ev0.elapsed_time(ev1) * 1e-3), 2), "unit": "frames/s",
+        "note": "one frame at a time: student pair, agreement count read by the host, teacher "
+                "pair when below the threshold, consistency step"}
+    # 3840x2160: student vs teacher, BF16 streaming
+    log("student 4K: generating frames")
+    sc4 = synth.LayeredScene(3840, 2160, seed=7)
+    dev = I[0].device
+    I4 = [sc4.frame(t, device=dev)[None].contiguous() for t in range(6)]
+    P4 = [synth.stylize(x[0], t)[None].contiguous() for t, x in enumerate(I4)]
+    K4 = max(20, K // 4)
+    r4 = measure(tcflow, dict(sd, height=2160, width=3840), wts, tcflow.TC_BF16, I4, P4, K4,
+                 max(2, W // 4), len(I4))
+    t4 = measure(tcflow, dict(td, height=2160, width=3840), synth.he_weights(td), tcflow.TC_BF16,
+                 I4, P4, K4, max(2, W // 4), len(I4))
+    out["bf16_4k"] = {"value": round(r4["fps"], 2), "unit": "frames/s",
+                      "teacher_bf16_value": round(t4["fps"], 2),
+                      "speedup_vs_teacher_bf16": round(r4["fps"] / t4["fps"], 3),
+                      "p99_frame_ms": round(float(np.percentile(r4["lat"], 99)), 4)}
+    # training step rate, measured live
+    h, w = sd["height"], sd["width"]
+    A, B = stu.make_pairs(16, h, w, device=dev)
+    Tf, Tb = stu.teacher_flows(teacher, A, B)
+    tp = sd["train"]
+    nsteps = 30
+    _, _, secs = stu.train(sd, A, B, Tf, Tb, nsteps, tp["batch"], weights=wts,
+                           params=tcflow.train_params(lr=tp["lr"]), log_every=10 ** 9)
+    out["train_step_ms"] = round(1e3 * secs / nsteps, 3)
+    out["train_note"] = (f"batch {tp['batch']} pairs at {w}x{h}, FP32 forward + hand-written "
+                         "backward + AdamW, timed over 30 steps")
+    return out
 
 
 def serve_leg(tcflow, desc, blob, nframes, unique=6):

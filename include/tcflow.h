@@ -209,6 +209,14 @@ TC_API int tc_consistency_paper(const float* I_prev, const float* I, const float
 
 /* ---- measurement probe -------------------------------------------------- */
 
+/* Forward-backward agreement of a flow pair: counts[i] (device, n
+ * unsigned) = number of pixels of image i that pass the test of
+ * tc_consistency_step's mask (target inside the frame and
+ * |f_b + f~_f|^2 <= 0.01 (|f_b|^2 + |f~_f|^2) + 0.5).  Used to fall back from
+ * a student network's flows to the teacher's when too few pixels agree. */
+TC_API int tc_flow_agreement(const float* flow_fw, const float* flow_bw, int n, int h, int w,
+                             unsigned* counts, void* stream);
+
 /* ---- training of a student network on teacher flows --------------------
  *
  * Paper Sec. 3.2 ("Training") and the supplementary loss: the loss is a sum

@@ -941,6 +941,14 @@ int tc_consistency_step(const float* stylized, const float* prev_out, const floa
   return e == hipSuccess ? TC_OK : TC_ERR_HIP;
 }
 
+int tc_flow_agreement(const float* flow_fw, const float* flow_bw, int n, int h, int w,
+                      unsigned* counts, void* stream) {
+  if (!flow_fw || !flow_bw || !counts || !shape_ok(n, h, w)) return TC_ERR_INVALID_ARG;
+  return launch_agreement(flow_fw, flow_bw, n, h, w, counts, (hipStream_t)stream) == hipSuccess
+             ? TC_OK
+             : TC_ERR_HIP;
+}
+
 void tc_paper_default_params(tc_paper_params* p) {
   if (!p) return;
   p->k1 = 0.3f;

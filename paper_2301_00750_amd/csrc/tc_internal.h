@@ -197,6 +197,11 @@ struct PaperArgs {
 };
 hipError_t launch_paper_step(const PaperArgs& a, float* out, int block_iters, hipStream_t s);
 
+// counts[i] = pixels of image i passing the forward-backward test of the
+// consistency step (flows n x 2 x h x w).
+hipError_t launch_agreement(const float* ffw, const float* fbw, int n, int h, int w,
+                            unsigned* counts, hipStream_t s);
+
 hipError_t launch_consistency(const float* P, const float* Oprev, const float* ffw,
                               const float* fbw, float alpha, int n, int h, int w, float* out,
                               unsigned char* mask, hipStream_t s);

@@ -27,7 +27,7 @@ EXPORTS = (
     "tc_paper_default_params", "tc_paper_workspace_bytes", "tc_consistency_paper",
     "tc_fp8_e4m3_encode", "tc_decoder_list_workspace_bytes", "tc_flow_from_pyramid_list",
     "tc_train_default_params", "tc_trainer_create", "tc_trainer_destroy", "tc_trainer_grad",
-    "tc_trainer_step", "tc_trainer_copy", "tc_trainer_steps_done",
+    "tc_trainer_step", "tc_trainer_copy", "tc_trainer_steps_done", "tc_flow_agreement",
 )
 
 (TC_OP_PYR_A, TC_OP_PYR_B, TC_OP_UP2, TC_OP_COST_VOLUME, TC_OP_C1, TC_OP_C2, TC_OP_C3, TC_OP_HEAD,
@@ -122,6 +122,7 @@ def _load():
         "tc_trainer_step": (ci, [vp, vp, vp, vp, ci, vp, vp]),
         "tc_trainer_copy": (ci, [vp, ci, vp, vp]),
         "tc_trainer_steps_done": (ci, [vp]),
+        "tc_flow_agreement": (ci, [vp, vp, ci, ci, ci, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -283,6 +284,20 @@ def consistency_step(stylized, prev_out, flow_fw, flow_bw, alpha, out=None, mask
         _ptr(stylized), _ptr(prev_out), _ptr(flow_fw), _ptr(flow_bw), float(alpha), n, h, w,
         _ptr(o), _ptr(m), _stream(stream)))
     return (o, m) if mask else o
+
+
+def flow_agreement(flow_fw, flow_bw, counts=None, stream=None):
+    """Per image, the number of pixels passing the forward-backward test
+    (tc_flow_agreement), as a cuda int32 tensor (values are unsigned)."""
+    _frames(flow_fw, "flow_fw", 2)
+    _frames(flow_bw, "flow_bw", 2)
+    n, _, h, w = flow_fw.shape
+    if flow_bw.shape != flow_fw.shape:
+        raise ValueError("flow_agreement: shapes differ")
+    c = counts if counts is not None else torch.empty(n, dtype=torch.int32, device=flow_fw.device)
+    _check("tc_flow_agreement", _lib.tc_flow_agreement(_ptr(flow_fw), _ptr(flow_bw), n, h, w,
+                                                       _ptr(c), _stream(stream)))
+    return c
 
 
 def paper_params(**kw):

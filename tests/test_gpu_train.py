@@ -105,3 +105,40 @@ def test_training_lowers_loss(tc):
     last = float(tr.grad(A, B, T))
     say(f"   loss {first:.4f} -> {last:.4f}")
     assert np.isfinite(last) and last < 0.9 * first
+
+
+def test_flow_agreement_counts(tc):
+    """Counts equal the consistency step's mask and the oracle's mask away
+    from its undecided band."""
+    gen = torch.Generator().manual_seed(3)
+    h, w = 67, 91
+    ffw = 3 * torch.randn(2, 2, h, w, generator=gen)
+    fbw = -ffw + 0.5 * torch.randn(2, 2, h, w, generator=gen)
+    g = [x.cuda().contiguous() for x in (ffw, fbw)]
+    say("[agreement] 2 x 67x91")
+    counts = tc.flow_agreement(*g).cpu().numpy()
+    P = torch.rand(2, 3, h, w, generator=gen).cuda()
+    _, m = tc.consistency_step(P, P.clone(), g[0], g[1], 0.5, mask=True)
+    assert np.array_equal(counts, m.reshape(2, -1).sum(1).cpu().numpy())
+    for i in range(2):
+        _, rm, margin, _ = O.consistency(np.zeros((3, h, w)), np.zeros((3, h, w)),
+                                         ffw[i].double().numpy(), fbw[i].double().numpy(), 0.5)
+        amb = int((np.abs(margin) <= 1e-4).sum())
+        assert abs(int(counts[i]) - int(rm.sum())) <= amb
+
+
+def test_fallback_switches_to_teacher(tc):
+    from paper_2301_00750_amd import student
+    sd, td = synth.load_desc("student"), synth.load_desc("tiny")
+    s_net, t_net = tc.Net(sd, synth.he_weights(sd)), tc.Net(td, synth.he_weights(td))
+    A, B, _ = batch(1, 64, 96, 4)
+    A, B = A.cuda().contiguous(), B.cuda().contiguous()
+    say("[fallback] thresholds 0 and 1.01")
+    never = student.FallbackFlow(s_net, t_net, 64, 96, threshold=0.0)
+    fw, bw, agree = never(A, B)
+    sfw, sbw = s_net.flow_estimate_pair(A, B)
+    assert torch.equal(fw, sfw) and never.fallbacks == 0 and 0.0 <= agree <= 1.0
+    always = student.FallbackFlow(s_net, t_net, 64, 96, threshold=1.01)
+    fw, bw, _ = always(A, B)
+    tfw, tbw = t_net.flow_estimate_pair(A, B)
+    assert torch.equal(fw, tfw) and torch.equal(bw, tbw) and always.fallbacks == 1
