@@ -381,24 +381,46 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
+  // Chunk-invariant index math, hoisted out of the K loop: the image bases
+  // of the two input views, the staging slot (channel block, pixel offset)
+  // of each of this thread's input words, and the LDS offset of this lane's
+  // A operand for every MFMA step of a full and of a half chunk.
+  const bf16* base0 = view_base_t<bf16>(a.in0, img, in_plane * a.in0.cbt);
+  const bf16* base1 = view_base_t<bf16>(a.in1, img, in_plane * a.in1.cbt);
+  int f_cbi[RA], f_off[RA];
+#pragma unroll
+  for (int j = 0; j < RA; ++j) {
+    const int i = tid + j * 256;
+    const int cbi = i / NPOS, pos = i - (i / NPOS) * NPOS;
+    const int py = pos / IW, px = pos - (pos / IW) * IW;
+    const int gy = iy0 + py, gx = ix0 + px;
+    f_cbi[j] = cbi;
+    f_off[j] = (i < NA && gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w) ? gy * a.in_w + gx : -1;
+  }
+  const int lm = lane & 15, lk = lane >> 4;
+  int a_full[BF_STEPS], a_half[BF_STEPS];
+#pragma unroll
+  for (int st = 0; st < BF_STEPS; ++st) {
+    const int kb = 4 * st + lk;
+    // full chunk: (tap, block) pairs block fastest, 2 blocks
+    const int tf = kb < 9 * BF_CPC ? kb / BF_CPC : 0, cf = kb < 9 * BF_CPC ? kb % BF_CPC : 0;
+    a_full[st] = cf * NPOS + (tf / 3) * IW + (tf % 3) + lm * S;
+    // half chunk (the last one when the block count is odd): 1 block
+    const int th = kb < 9 ? kb : 0;
+    a_half[st] = (th / 3) * IW + (th % 3) + lm * S;
+  }
+
   u4 ra[RA];
   W rb[RB];
   auto fetch = [&](int ch) {
 #pragma unroll
     for (int j = 0; j < RA; ++j) {
-      const int i = tid + j * 256;
       u4 val = u4{0u, 0u, 0u, 0u};
-      if (i < NA) {
-        const int cbi = i / NPOS, pos = i - cbi * NPOS;
-        const int b = ch * BF_CPC + cbi;
-        const int py = pos / IW, px = pos - py * IW;
-        const int gy = iy0 + py, gx = ix0 + px;
-        if (b < nblk && gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w) {
-          const View& v = b < a.nb0 ? a.in0 : a.in1;
-          const int cb = (b < a.nb0 ? b : b - a.nb0) + v.cb0;
-          const bf16* src = view_base_t<bf16>(v, img, in_plane * v.cbt) + (size_t)cb * in_plane;
-          val = *reinterpret_cast<const u4*>(src + ((size_t)gy * a.in_w + gx) * 8);
-        }
+      const int b = ch * BF_CPC + f_cbi[j];
+      if (f_off[j] >= 0 && b < nblk) {
+        const bf16* src = b < a.nb0 ? base0 + (size_t)(b + a.in0.cb0) * in_plane
+                                    : base1 + (size_t)(b - a.nb0 + a.in1.cb0) * in_plane;
+        val = *reinterpret_cast<const u4*>(src + (size_t)f_off[j] * 8);
       }
       ra[j] = val;
     }
@@ -430,29 +452,24 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
     }
   };
 
-  const int lm = lane & 15, lk = lane >> 4;
   if (c_begin < c_end) fetch(c_begin);
   for (int ch = c_begin; ch < c_end; ++ch) {
     stash();
     __syncthreads();
     if (ch + 1 < c_end) fetch(ch + 1);
-    const int cpc = min(BF_CPC, nblk - ch * BF_CPC);
-    const int nk = 9 * cpc;
-    const int steps = (nk + 3) / 4;
+    const bool full = nblk - ch * BF_CPC >= BF_CPC;
+    const int steps = full ? BF_STEPS : (9 + 3) / 4;
 #pragma unroll
     for (int st = 0; st < BF_STEPS; ++st) {
       if (st < steps) {
-        const int kb = 4 * st + lk;
-        const bool ok = kb < nk;
-        const int tap = ok ? kb / cpc : 0, cbi = ok ? kb - (kb / cpc) * cpc : 0;
-        const int p = tap / 3, q = tap - (tap / 3) * 3;
+        const int aoff = full ? a_full[st] : a_half[st];
         W fb[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) fb[nb] = sB[(st * 4 + lk) * NP + nb * 16 + lm];
 #pragma unroll
         for (int mb = 0; mb < MR; ++mb) {
           const int r = wave * MR + mb;
-          const W fa = sA[cbi * NPOS + (r * S + p) * IW + lm * S + q];
+          const W fa = sA[aoff + r * S * IW];
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
             if constexpr (F8)
