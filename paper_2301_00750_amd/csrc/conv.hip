@@ -354,8 +354,8 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
   constexpr int NA = BF_CPC * NPOS;        // operand words of input per chunk
   constexpr int NBW = BF_STEPS * 4 * NP;   // operand words of weights per chunk
   constexpr int RA = (NA + 255) / 256, RB = (NBW + 255) / 256;
-  __shared__ W sA[NA];
-  __shared__ W sB[NBW];
+  __shared__ __attribute__((aligned(16))) W sA[NA];
+  __shared__ __attribute__((aligned(16))) W sB[NBW];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -486,27 +486,68 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
   }
 
   float mx = 0.f;
+  if (a.splits == 1 && !a.compact && !a.add) {
+    // Blocked bfloat16 output: per output row, each wave writes its 16 x NP
+    // results to LDS ([pixel][channel]) and stores them back as 16-byte
+    // words (8 channels of one pixel), coalesced, instead of one 2-byte
+    // store per value.  The staging buffers are free after the K loop.
+    bf16* so = reinterpret_cast<bf16*>(sB) + (size_t)wave * (TW * NP);
+    const size_t plane = (size_t)a.out_h * a.out_w;
 #pragma unroll
-  for (int mb = 0; mb < MR; ++mb) {
-    const int oy = ty0 + wave * MR + mb;
-    if (oy >= a.out_h) continue;
+    for (int mb = 0; mb < MR; ++mb) {
+      const int oy = ty0 + wave * MR + mb;
+      __syncthreads();
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int n = nb * 16 + lm;
-      if (n >= a.cout) continue;
-      const float osc = F8 ? sa * a.wscale[n] : 1.f;
+      for (int nb = 0; nb < NB; ++nb) {
+        const int n = nb * 16 + lm;
+        const bool nok = n < a.cout;
+        const float osc = F8 ? sa * a.wscale[n] : 1.f;
+        const float bn = nok ? a.b[n] : 0.f;
 #pragma unroll
-      for (int vv = 0; vv < 4; ++vv) {
-        const int ox = tx0 + 4 * lk + vv;
-        if (ox >= a.out_w) continue;
-        const float accv = acc[mb][nb][vv] * osc;
-        if (a.splits > 1) {
-          a.partial[((((size_t)split * a.n + img) * a.out_h + oy) * a.out_w + ox) * NP + n] = accv;
-        } else {
-          const size_t pix = ((size_t)img * a.out_h + oy) * a.out_w + ox;
-          const float v = finish(a, accv, n, pix);
-          mx = fmaxf(mx, fabsf(v));
-          store_out<bf16>(a, v, img, oy, ox, n);
+        for (int vv = 0; vv < 4; ++vv) {
+          const int px = 4 * lk + vv;
+          float v = acc[mb][nb][vv] * osc + bn;
+          if (a.lrelu) v = v >= 0.f ? v : a.slope * v;
+          if (nok && oy < a.out_h && tx0 + px < a.out_w) mx = fmaxf(mx, fabsf(v));
+          so[px * NP + n] = f2bf(v);
+        }
+      }
+      __syncthreads();
+      if (oy < a.out_h) {
+        for (int e = lane; e < TW * (NP / 8); e += 64) {
+          const int px = e / (NP / 8), blk = e - (e / (NP / 8)) * (NP / 8);
+          const int ox = tx0 + px;
+          if (ox < a.out_w && blk * 8 < a.cout)
+            *reinterpret_cast<u4*>(reinterpret_cast<bf16*>(a.out) +
+                                   (((size_t)img * a.out_cbt + a.out_cb0 + blk) * plane +
+                                    (size_t)oy * a.out_w + ox) * 8) =
+                *reinterpret_cast<const u4*>(so + px * NP + blk * 8);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int mb = 0; mb < MR; ++mb) {
+      const int oy = ty0 + wave * MR + mb;
+      if (oy >= a.out_h) continue;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int n = nb * 16 + lm;
+        if (n >= a.cout) continue;
+        const float osc = F8 ? sa * a.wscale[n] : 1.f;
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+          const int ox = tx0 + 4 * lk + vv;
+          if (ox >= a.out_w) continue;
+          const float accv = acc[mb][nb][vv] * osc;
+          if (a.splits > 1) {
+            a.partial[((((size_t)split * a.n + img) * a.out_h + oy) * a.out_w + ox) * NP + n] = accv;
+          } else {
+            const size_t pix = ((size_t)img * a.out_h + oy) * a.out_w + ox;
+            const float v = finish(a, accv, n, pix);
+            mx = fmaxf(mx, fabsf(v));
+            store_out<bf16>(a, v, img, oy, ox, n);
+          }
         }
       }
     }
