@@ -180,6 +180,47 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_mfma(ConvArgs a) {
   }
 
   // ---- epilogue
+  constexpr int NPS = NP + 4;
+  constexpr bool kFits = 9 * KC * BPITCH >= 4 * TW * NPS;  // LDS rows for the 4 waves
+  if (kFits && a.splits == 1 && !a.compact && !a.add) {
+    // Blocked output: per output row, each wave writes its 16 x NP results
+    // to LDS ([pixel][channel], rows padded by 4 floats so the four lane
+    // groups hit different banks) and stores them back as whole 32-byte
+    // blocks (8 channels of one pixel).  The staging buffers are free now.
+    float* so = sB + wave * (TW * NPS);
+    const size_t plane = (size_t)a.out_h * a.out_w;
+#pragma unroll
+    for (int mb = 0; mb < MR; ++mb) {
+      const int oy = ty0 + wave * MR + mb;
+      __syncthreads();
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int n = nb * 16 + lm;
+        const float bn = n < a.cout ? a.b[n] : 0.f;
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+          float v = acc[mb][nb][vv] + bn;
+          if (a.lrelu) v = v >= 0.f ? v : a.slope * v;
+          so[(4 * lk + vv) * NPS + n] = v;
+        }
+      }
+      __syncthreads();
+      if (oy < a.out_h) {
+        for (int e = lane; e < TW * (NP / 8); e += 64) {
+          const int px = e / (NP / 8), blk = e - (e / (NP / 8)) * (NP / 8);
+          const int ox = tx0 + px;
+          if (ox < a.out_w && blk * 8 < a.cout) {
+            const f4* src = reinterpret_cast<const f4*>(so + px * NPS + blk * 8);
+            f4* dst = reinterpret_cast<f4*>(
+                a.out + (((size_t)img * a.out_cbt + a.out_cb0 + blk) * plane + (size_t)oy * a.out_w + ox) * 8);
+            dst[0] = src[0];
+            dst[1] = src[1];
+          }
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int mb = 0; mb < MR; ++mb) {
     const int oy = ty0 + wave * MR + mb;
