@@ -187,7 +187,7 @@ DecLayout dec_layout(const tc_net* net, int nb, int h, int w) {
   L.R[1] = take(px * rw * net->esz);
   size_t part = 0;
   for (int l = f; l <= net->d.levels; ++l)
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
       const size_t pb = layer_partial_bytes(net->dec[l - 1][k], g.h[l], g.w[l], nb, 1);
       if (pb > part) part = pb;
     }
@@ -399,11 +399,11 @@ int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, in
   a.partial = partial;
   hipError_t e;
   probe_begin(stage, s);
-  if (L.cout == 2 && compact && stride == 1 && L.kc == 8) {  // estimator head
+  if (!act_bf16 && L.cout == 2 && compact && stride == 1 && L.kc == 8) {
+    // FP32 estimator head on vector ALUs
     a.splits = 1;
     a.nchunks = L.cin_pad / 8;
     a.cps = a.nchunks;
-    a.bf16act = act_bf16;
     e = launch_head(a, s);
   } else {
     const ConvPlan p = plan_conv(out_h, out_w, n, a.nchunks, stride, L.np);
@@ -676,7 +676,7 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     Packed pk;
     int np = 0;
     cl.fp8 = net->fp8 && !head && fp8_ok;
-    cl.bf16 = net->bf16act && !head && !cl.fp8;
+    cl.bf16 = net->bf16act && !cl.fp8;
     cl.ws = nullptr;
     if (cl.fp8) {
       std::vector<uint8_t> wq;

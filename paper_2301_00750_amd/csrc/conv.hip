@@ -1,6 +1,9 @@
 // 3x3 convolution (zero padding 1, stride 1 or 2) as an implicit GEMM on the
-// FP32 matrix cores of gfx950 (v_mfma_f32_16x16x4_f32), plus the 2-channel
-// estimator head on vector ALUs.
+// matrix cores of gfx950: FP32 (v_mfma_f32_16x16x4_f32), BF16 and FP8 forms.
+// The 2-channel estimator heads: on vector ALUs for FP32 activations (one
+// 16-channel MFMA N block would waste 7/8 of the FP32 matrix rate), on the
+// BF16 MFMA kernel otherwise (flow output with the upsampled flow added in
+// the epilogue).
 //
 // GEMM view: M = output pixels, N = output channels, K = 9 taps x input
 // channels.  A workgroup (4 waves) owns a (4 * MR) x 16 tile of output pixels
@@ -245,6 +248,42 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_mfma(ConvArgs a) {
   }
 }
 
+// Sum of the split-K partials in split order, then bias / LeakyReLU / store,
+// for blocked outputs: one thread per (pixel, block of 8 channels), vector
+// loads of the partials and one whole-block store.
+template <typename T>
+__global__ __launch_bounds__(256) void conv_reduce8_kernel(ConvArgs a) {
+  const int img = blockIdx.y;
+  const size_t pixels = (size_t)a.n * a.out_h * a.out_w;
+  const size_t plane = (size_t)a.out_h * a.out_w;
+  const int nbo = a.cout / 8;
+  const size_t per = plane * nbo;
+  float mx = 0.f;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int blk = (int)(i % nbo);
+    const size_t p = i / nbo;
+    const size_t pix = (size_t)img * plane + p;
+    float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < a.splits; ++k) {
+      float t[8];
+      load8(a.partial + ((size_t)k * pixels + pix) * a.np + blk * 8, t);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) v[c] += t[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      v[c] += a.b[blk * 8 + c];
+      if (a.lrelu) v[c] = v[c] >= 0.f ? v[c] : a.slope * v[c];
+      mx = fmaxf(mx, fabsf(v[c]));
+    }
+    store8(reinterpret_cast<T*>(a.out) +
+               (((size_t)img * a.out_cbt + a.out_cb0 + blk) * plane + p) * 8,
+           v);
+  }
+  if (a.aout) record_amax(a.aout + (size_t)img * kAmaxWords, mx);
+}
+
 // Sum of the split-K partials in split order, then bias / LeakyReLU / add / store.
 template <typename T>
 __global__ __launch_bounds__(256) void conv_reduce_kernel(ConvArgs a) {
@@ -270,7 +309,7 @@ __global__ __launch_bounds__(256) void conv_reduce_kernel(ConvArgs a) {
 
 // ---------------------------------------------------------------- head
 //
-// Two output channels on vector ALUs.  A workgroup owns 8 x 32 output
+// Two output channels on vector ALUs (FP32 activations).  A workgroup owns 8 x 32 output
 // pixels; its 4 waves split the input-channel chunks (wave w takes chunks
 // w, w + 4, ...) and each lane accumulates 4 pixels (rows r, r + 2, r + 4,
 // r + 6 of its column), so every weight read from LDS feeds 8 FMAs.  The
@@ -685,6 +724,14 @@ hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, int mr, hipStre
   else if (stride == 2 && kc == 4 && mr == 2) e = dispatch_nb<2, 4, 2>(a, s);
   else if (stride == 1 && kc == 4 && mr == 2) e = dispatch_nb<1, 4, 2>(a, s);
   if (e != hipSuccess || a.splits == 1) return e;
+  if (!a.compact && !a.add && a.cout % 8 == 0) {
+    const dim3 g(grid_1d((size_t)a.out_h * a.out_w * (a.cout / 8)), a.n);
+    if (a.bf16act)
+      conv_reduce8_kernel<bf16><<<g, 256, 0, s>>>(a);
+    else
+      conv_reduce8_kernel<float><<<g, 256, 0, s>>>(a);
+    return hipGetLastError();
+  }
   const dim3 g(grid_1d((size_t)a.out_h * a.out_w * a.cout), a.n);
   if (a.bf16act)
     conv_reduce_kernel<bf16><<<g, 256, 0, s>>>(a);

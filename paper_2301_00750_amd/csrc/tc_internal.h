@@ -102,7 +102,8 @@ ConvPlan plan_conv(int out_h, int out_w, int n, int nchunks, int stride, int np)
 size_t conv_partial_bytes(const ConvPlan& p, int out_h, int out_w, int n, int np);
 
 hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, int mr, hipStream_t s);
-// 3x3 conv with two output channels (the estimator head) on vector ALUs.
+// 3x3 conv with two output channels (the estimator head) on vector ALUs,
+// FP32 activations.
 hipError_t launch_head(const ConvArgs& a, hipStream_t s);
 
 
