@@ -319,7 +319,8 @@ void pack_conv_fp8(const float* W, const float* b, int cout, int cin, int cin_pa
 // the order of the blob.
 struct SepPacked {
   std::vector<char> pw;
-  std::vector<float> rest;  // b [np], depthwise W [9][cin_pad], depthwise b [cin_pad]
+  std::vector<float> rest;  // b [np], depthwise W [9][cin_pad], depthwise b [cin_pad],
+                            // depthwise bfloat16 tap pairs [5][cin_pad] (bits)
 };
 
 void pack_sep(const SepLayer& L, const float* dw, const float* dwb, const float* pw,
@@ -345,12 +346,18 @@ void pack_sep(const SepLayer& L, const float* dw, const float* dwb, const float*
     out.pw.resize(nval * 4);
     memcpy(out.pw.data(), wf.data(), nval * 4);
   }
-  out.rest.assign((size_t)L.np + 10 * L.cin_pad, 0.f);
+  out.rest.assign((size_t)L.np + 15 * L.cin_pad, 0.f);
   for (int o = 0; o < L.cout; ++o) out.rest[o] = pb[o];
   float* dwo = out.rest.data() + L.np;
   for (int c = 0; c < L.cin; ++c) {
     for (int tap = 0; tap < 9; ++tap) dwo[(size_t)tap * L.cin_pad + c] = dw[(size_t)c * 9 + tap];
     dwo[(size_t)9 * L.cin_pad + c] = dwb[c];
+    for (int pr = 0; pr < 5; ++pr) {  // bfloat16 tap pairs for the BF16 form
+      const uint32_t lo = host_f2bf(dw[(size_t)c * 9 + 2 * pr]);
+      const uint32_t hi = 2 * pr + 1 < 9 ? host_f2bf(dw[(size_t)c * 9 + 2 * pr + 1]) : 0u;
+      const uint32_t word = lo | (hi << 16);
+      memcpy(dwo + (size_t)(10 + pr) * L.cin_pad + c, &word, 4);
+    }
   }
 }
 
@@ -799,6 +806,7 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     sl.b = reinterpret_cast<float*>(base + o1);
     sl.dw = sl.b + sl.np;
     sl.dwb = sl.dw + (size_t)9 * sl.cin_pad;
+    sl.dw2 = reinterpret_cast<const unsigned*>(sl.dwb + sl.cin_pad);
   }
   if (hipMemcpy(net->dmem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(net->dmem);

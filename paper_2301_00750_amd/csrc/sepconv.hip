@@ -10,6 +10,9 @@
 // LDS, and the taps of the next K chunk load while the current chunk
 // computes.  Workgroups are persistent over a contiguous range of tiles.
 //
+// Depthwise arithmetic: FP32 FMAs in the FP32 form; in the BF16 form
+// v_dot2_f32_bf16 over pairs of taps with bfloat16 weights (FP32 sums).
+//
 // FP32 form, v_mfma_f32_16x16x4_f32 with K chunks of 16 channels: lane group
 // g = l / 16 holds channels 4g .. 4g+3 of the chunk for pixel l % 16 and
 // feeds them to four MFMAs, one channel each (the weights are packed in the
@@ -93,7 +96,10 @@ __global__ __launch_bounds__(256, 2) void sepconv_mfma(SepLayer L, SepArgs a) {
   const int cin_pad = L.cin_pad;
   const int nchunks = cin_pad / K;
   stage_lds(s_pw, reinterpret_cast<const Frag*>(L.pw), nchunks * NB * 64);
-  stage_lds(s_dw, reinterpret_cast<const f4*>(L.dw), 9 * cin_pad / 4);
+  if constexpr (BF)  // depthwise weights as bfloat16 pairs of taps (2p, 2p+1), p < 5
+    stage_lds(reinterpret_cast<u4*>(s_dw), reinterpret_cast<const u4*>(L.dw2), 5 * cin_pad / 4);
+  else
+    stage_lds(s_dw, reinterpret_cast<const f4*>(L.dw), 9 * cin_pad / 4);
   stage_lds(s_dwb, reinterpret_cast<const f4*>(L.dwb), cin_pad / 4);
   __syncthreads();
 
@@ -156,19 +162,52 @@ __global__ __launch_bounds__(256, 2) void sepconv_mfma(SepLayer L, SepArgs a) {
         const f4 b4 = s_dwb[ch0 / 4 + i];
         t[4 * i] = b4.x; t[4 * i + 1] = b4.y; t[4 * i + 2] = b4.z; t[4 * i + 3] = b4.w;
       }
+      if constexpr (BF) {
+        // Two taps at a time on v_dot2_f32_bf16: for a channel c the pair
+        // (x_a[c], x_b[c]) is gathered from the two taps' words with one
+        // v_perm_b32 and dotted with the packed weights (w[c][a], w[c][b]).
+        const unsigned* s_w2 = reinterpret_cast<const unsigned*>(s_dw);
+        u4 wp[5][2];
 #pragma unroll
-      for (int tap = 0; tap < 9; ++tap) {
-        Raw r = raw[tap];
-        if (!interior && off[tap] < 0) r = Raw{};
-        float v[CH];
-        unpack_raw<BF>(r, v);
+        for (int pr = 0; pr < 5; ++pr) {
+          wp[pr][0] = *reinterpret_cast<const u4*>(s_w2 + pr * cin_pad + ch0);
+          wp[pr][1] = *reinterpret_cast<const u4*>(s_w2 + pr * cin_pad + ch0 + 4);
+        }
 #pragma unroll
-        for (int i = 0; i < CH / 4; ++i) {
-          const f4 w4 = s_dw[(tap * cin_pad + ch0) / 4 + i];
-          t[4 * i] += w4.x * v[4 * i];
-          t[4 * i + 1] += w4.y * v[4 * i + 1];
-          t[4 * i + 2] += w4.z * v[4 * i + 2];
-          t[4 * i + 3] += w4.w * v[4 * i + 3];
+        for (int pr = 0; pr < 5; ++pr) {
+          Raw ra_ = raw[2 * pr];
+          if (!interior && off[2 * pr] < 0) ra_ = Raw{};
+          Raw rb_ = Raw{};
+          if (pr < 4) {
+            rb_ = raw[2 * pr + 1];
+            if (!interior && off[2 * pr + 1] < 0) rb_ = Raw{};
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const unsigned p0 = __builtin_amdgcn_perm(ra_[j], rb_[j], 0x01000504u);
+            const unsigned p1 = __builtin_amdgcn_perm(ra_[j], rb_[j], 0x03020706u);
+            const unsigned w0 = wp[pr][j >> 1][2 * (j & 1)], w1 = wp[pr][j >> 1][2 * (j & 1) + 1];
+            t[2 * j] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, p0),
+                                                       __builtin_bit_cast(bf16x2, w0), t[2 * j], false);
+            t[2 * j + 1] = __builtin_amdgcn_fdot2_f32_bf16(
+                __builtin_bit_cast(bf16x2, p1), __builtin_bit_cast(bf16x2, w1), t[2 * j + 1], false);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+          Raw r = raw[tap];
+          if (!interior && off[tap] < 0) r = Raw{};
+          float v[CH];
+          unpack_raw<BF>(r, v);
+#pragma unroll
+          for (int i = 0; i < CH / 4; ++i) {
+            const f4 w4 = s_dw[(tap * cin_pad + ch0) / 4 + i];
+            t[4 * i] += w4.x * v[4 * i];
+            t[4 * i + 1] += w4.y * v[4 * i + 1];
+            t[4 * i + 2] += w4.z * v[4 * i + 2];
+            t[4 * i + 3] += w4.w * v[4 * i + 3];
+          }
         }
       }
 #pragma unroll

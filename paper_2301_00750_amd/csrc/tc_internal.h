@@ -165,6 +165,7 @@ struct SepLayer {
   int bf16;         // BF16 operands (chunks of 32 channels), else FP32 (16)
   float* dw;        // device [9][cin_pad] depthwise weights (tap = 3 p + q), FP32
   float* dwb;       // device [cin_pad]
+  const unsigned* dw2;  // device [5][cin_pad]: bfloat16 pairs (w[c][2p], w[c][2p+1]), w[c][9] = 0
   void* pw;         // device, packed [cin_pad / chunk][np / 16][64 lanes][chunk / 4]
   float* b;         // device [np]
 };
