@@ -204,7 +204,7 @@ def main():
                     help="comma-separated precision forms measured after the FP32 path ('' = none)")
     ap.add_argument("--paper-steps", type=int, default=30,
                     help="1080p frames of the paper's full consistency step to time (0 = skip)")
-    ap.add_argument("--serve-frames", type=int, default=90,
+    ap.add_argument("--serve-frames", type=int, default=300,
                     help="frames per stream of the 16-stream serving mix (0 = skip)")
     ap.add_argument("--variants", default="fullhd_sepref",
                     help="comma-separated network variants (configs) measured in every precision "
@@ -418,11 +418,13 @@ def student_leg(tcflow, nets, I, P, K, W, frames, base_fps):
                          "p99_frame_ms": round(float(np.percentile(rs["lat"], 99)), 4)}
     s_bf16 = rs["net"]
     s_fp32 = tcflow.Net(sd, wts)
+    s_init = tcflow.Net(sd, synth.he_weights(sd))  # the same network before training
     teacher = nets["fp32"]
     teacher_fast = nets.get("bf16", teacher)
     # EPE against the FP32 teacher and the agreement fallback, frame by frame
     fb = stu.FallbackFlow(s_bf16, teacher_fast, H, W_, threshold=0.9)
-    epe_s, epe_s32, epe_out, agrees, t_agrees, rms = [], [], [], [], [], []
+    epe_s, epe_s32, epe_out, epe_init, epe_zero = [], [], [], [], []
+    agrees, t_agrees, rms = [], [], []
     nf = min(12, len(I) - 1)
     for t in range(1, nf + 1):
         tf, tb = teacher.flow_estimate_pair(I[t - 1], I[t])
@@ -431,13 +433,18 @@ def student_leg(tcflow, nets, I, P, K, W, frames, base_fps):
         sf, sb = s_fp32.flow_estimate_pair(I[t - 1], I[t])
         f, b, agree = fb(I[t - 1], I[t])
         bf, bb = s_bf16.flow_estimate_pair(I[t - 1], I[t])
+        uf, ub = s_init.flow_estimate_pair(I[t - 1], I[t])
+        zero = torch.zeros_like(tf)
         for x, y, acc in ((bf, tf, epe_s), (bb, tb, epe_s), (sf, tf, epe_s32), (sb, tb, epe_s32),
-                          (f, tf, epe_out), (b, tb, epe_out)):
+                          (f, tf, epe_out), (b, tb, epe_out), (uf, tf, epe_init),
+                          (ub, tb, epe_init), (zero, tf, epe_zero), (zero, tb, epe_zero)):
             acc.append(float(torch.sqrt(((x - y) ** 2).sum(1)).mean()))
         agrees.append(agree)
     out["epe_vs_teacher_px"] = {"student_bf16": round(float(np.mean(epe_s)), 4),
                                 "student_fp32": round(float(np.mean(epe_s32)), 4),
                                 "with_fallback": round(float(np.mean(epe_out)), 4),
+                                "untrained_student_fp32": round(float(np.mean(epe_init)), 4),
+                                "zero_flow": round(float(np.mean(epe_zero)), 4),
                                 "teacher_flow_rms_px": round(float(np.mean(rms)), 3),
                                 "frames": nf}
     out["fallback"] = {"threshold": 0.9, "rate": round(fb.fallbacks / max(1, fb.frames), 4),
@@ -491,86 +498,171 @@ def student_leg(tcflow, nets, I, P, K, W, frames, base_fps):
     return out
 
 
-def serve_leg(tcflow, desc, blob, nframes, unique=6):
+def serve_leg(tcflow, desc, blob, nframes, unique=6, sat_frames=60):
     """16 concurrent streams, 4 each at 640x360, 1280x720, 1920x1080 and
     3840x2160, Poisson frame arrivals at 30 frames/s per stream, BF16 net,
-    continuous batching per resolution (paper_2301_00750_amd.serve)."""
+    continuous batching per resolution with each pass a replayed HIP graph
+    (paper_2301_00750_amd.serve).  Also the mix's capacity: every frame
+    available at once, with and without the graphs."""
     from paper_2301_00750_amd import serve
     dev = torch.device("cuda:0")
     net = tcflow.Net(desc, blob, precision=tcflow.TC_BF16)
     res = [(360, 640), (720, 1280), (1080, 1920), (2160, 3840)]
-    jobs = []
+    frames = []
     for ri, (h, w) in enumerate(res):
         for k in range(4):
             sid = 4 * ri + k
             sc = synth.LayeredScene(w, h, seed=100 + sid)
             I = [sc.frame(t, device=dev)[None].contiguous() for t in range(unique)]
             P = [synth.stylize(x[0], t)[None].contiguous() for t, x in enumerate(I)]
-            jobs.append(serve.StreamJob(sid, I, P, serve.poisson_arrivals(nframes, 30.0, 1000 + sid),
-                                        alpha=0.5))
+            frames.append((sid, I, P))
+
+    def jobs_for(n, poisson):
+        return [serve.StreamJob(sid, I, P, serve.poisson_arrivals(n, 30.0, 1000 + sid)
+                                if poisson else np.zeros(n), alpha=0.5)
+                for sid, I, P in frames]
+
     torch.cuda.synchronize()
     free = torch.cuda.mem_get_info(dev)[0]
-    srv = serve.Server(net, int(0.8 * free))
-    log(f"serving: 16 streams x {nframes} frames")
+
+    def per_res(jobs):
+        per = {}
+        for ri, (h, w) in enumerate(res):
+            lat = np.concatenate([np.asarray(j.latencies_ms) for j in jobs[4 * ri:4 * ri + 4]])
+            per[f"{w}x{h}"] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                               "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+        return per
+
+    log(f"serving (eager): 16 streams x {nframes} frames")
+    s_eager = serve.Server(net, int(0.8 * free))
+    e_jobs = jobs_for(nframes, True)
+    e_sum = s_eager.run(e_jobs)
+    s_eager.close()
+    srv = serve.Server(net, int(0.8 * free), graphs=True)
+    log("serving (graphs): warm-up session, 100 frames per stream")
+    srv.run(jobs_for(100, True))  # captures the passes the arrival pattern produces
+    warm_graphs = srv.graphs_captured
+    log(f"serving (graphs): 16 streams x {nframes} frames")
+    jobs = jobs_for(nframes, True)
     summary = srv.run(jobs)
-    per = {}
-    for ri, (h, w) in enumerate(res):
-        lat = np.concatenate([np.asarray(j.latencies_ms) for j in jobs[4 * ri:4 * ri + 4]])
-        per[f"{w}x{h}"] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
-                           "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+    per = per_res(jobs)
+    capacity = {}
+    for mode, graphs in (("hip_graphs", True), ("eager", False)):
+        log(f"serving capacity ({mode}): 16 streams x {sat_frames} frames, all available")
+        s2 = srv if graphs else serve.Server(net, int(0.8 * free))
+        s2.run(jobs_for(3, False))  # slots, and the graphs of the all-ready passes
+        r = s2.run(jobs_for(sat_frames, False))
+        capacity[mode] = round(r["frames_per_s"], 2)
+        if not graphs:
+            s2.close()
+    srv.close()
     return {
         "what": "16 streams (4 each at 640x360, 1280x720, 1920x1080, 3840x2160), Poisson arrivals "
-                f"at 30 frames/s per stream, {nframes} frames each, BF16, continuous batching",
+                f"at 30 frames/s per stream, {nframes} frames each, BF16, continuous batching, "
+                "one HIP graph launch per resolution pass",
         "offered_frames_per_s": 16 * 30,
         "aggregate_frames_per_s": round(summary["frames_per_s"], 2),
         "p50_latency_ms": round(summary["p50_ms"], 3),
         "p99_latency_ms": round(summary["p99_ms"], 3),
         "per_resolution": per,
         "wall_s": round(summary["wall_s"], 3),
+        "graphs_captured": {"warm_up": warm_graphs,
+                            "timed_session": summary["graphs_captured"] - warm_graphs},
+        "eager": {"aggregate_frames_per_s": round(e_sum["frames_per_s"], 2),
+                  "p50_latency_ms": round(e_sum["p50_ms"], 3),
+                  "p99_latency_ms": round(e_sum["p99_ms"], 3), "per_resolution": per_res(e_jobs)},
+        "capacity_frames_per_s": capacity,
+        "capacity_note": f"every frame of the mix available at once ({sat_frames} per stream): "
+                         "the frames/s the server sustains",
+        "graph_note": "graph passes read each frame from its stream's input slot, so the "
+                      "resident test frames are first copied there (in a deployment the upload "
+                      "lands there); eager passes read them in place",
     }
 
 
 def paper_leg(tcflow, net, I, P, steps, flow_ms):
-    """The paper's full consistency step (Eq. 2-7 weights + 150 momentum
+    """The paper's full consistency step (Eq. 2-7 weights + momentum
     iterations of the screened-Poisson energy) at 1920x1080 on flows from the
-    network; timed per call with HIP events on the current stream."""
+    network, for each of its parameter presets; timed with HIP events on the
+    current stream.  Per preset: the step alone, and a whole frame (the flow
+    pair (t, t+1) + the step at t) as one timed region; the fast preset takes
+    its flows from half-size inputs."""
     nfr = len(I)
-    fw, bw = [], []
-    for t in range(nfr - 1):  # flow pairs (t, t+1), computed outside the timing
-        a, b = net.flow_estimate_pair(I[t], I[t + 1])
-        fw.append(a)
-        bw.append(b)
-    prm = tcflow.paper_params()
+    H, W = I[0].shape[2], I[0].shape[3]
+    dev = I[0].device
     out = torch.empty_like(P[0])
-    ws = torch.empty(tcflow.lib().tc_paper_workspace_bytes(1, I[0].shape[2], I[0].shape[3]),
-                     dtype=torch.uint8, device=I[0].device)
-    Oprev = P[0].clone()
+    ws = torch.empty(tcflow.lib().tc_paper_workspace_bytes(1, H, W), dtype=torch.uint8, device=dev)
+    fws = {False: torch.empty(net.flow_workspace_bytes(1, H, W), dtype=torch.uint8, device=dev),
+           True: torch.empty(net.flow_half_workspace_bytes(1, H, W), dtype=torch.uint8,
+                             device=dev)}
+    cur_fw = torch.empty(1, 2, H, W, device=dev)
+    cur_bw = torch.empty_like(cur_fw)
 
-    def call(t):
-        # frame t uses flow t -> t-1 (backward flow of pair t-1) and t -> t+1
-        return tcflow.consistency_paper(I[t - 1], I[t], I[t + 1], P[t - 1], P[t], P[t + 1], Oprev,
-                                        bw[t - 1], fw[t], prm, out=out, ws=ws)
+    def pair(t, half, fw=None, bw=None):
+        f = net.flow_estimate_pair_half if half else net.flow_estimate_pair
+        return f(I[t], I[t + 1], ws=fws[half], out_fw=fw, out_bw=bw)
 
-    for t in range(1, 4):
-        call(t)
+    flows = {half: [pair(t, half) for t in range(nfr - 1)] for half in (False, True)}
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
-    for i in range(steps):
-        t = 1 + i % (nfr - 2)
-        ev[i][0].record()
-        call(t)
-        ev[i][1].record()
-        Oprev.copy_(out)
-    torch.cuda.synchronize()
-    ms = np.array([a.elapsed_time(b) for a, b in ev])
-    step_ms = float(np.median(ms))
+    # the half-size flows against the full-size ones (same network)
+    half_epe = float(np.mean([float(torch.sqrt(((a[0] - b[0]) ** 2).sum(1)).mean())
+                              for a, b in zip(flows[True][:4], flows[False][:4])]))
+    res, outs = {}, {}
+    for preset, half in (("final", False), ("objective", False), ("fast", True)):
+        prm = tcflow.paper_preset(preset)
+        fl = flows[half]
+        Oprev = P[0].clone()
+
+        def step(t, f_next=None):
+            # frame t uses flow t -> t-1 (backward flow of pair t-1) and t -> t+1
+            return tcflow.consistency_paper(I[t - 1], I[t], I[t + 1], P[t - 1], P[t], P[t + 1],
+                                            Oprev, fl[t - 1][1], fl[t][0] if f_next is None
+                                            else f_next, prm, out=out, ws=ws)
+
+        for t in range(1, 4):
+            step(t)
+        torch.cuda.synchronize()
+        outs[preset] = out.clone()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(2 * steps)]
+        for i in range(steps):  # the step alone
+            t = 1 + i % (nfr - 2)
+            ev[i][0].record()
+            step(t)
+            ev[i][1].record()
+            Oprev.copy_(out)
+        for i in range(steps):  # flow pair (t, t+1) + step
+            t = 1 + i % (nfr - 2)
+            e = ev[steps + i]
+            e[0].record()
+            pair(t, half, cur_fw, cur_bw)
+            step(t, cur_fw)
+            e[1].record()
+            Oprev.copy_(out)
+        torch.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in ev[:steps]])
+        fms = np.array([a.elapsed_time(b) for a, b in ev[steps:]])
+        res[preset] = {"k1": round(prm.k1, 4), "k2": round(prm.k2, 4), "a_ph": round(prm.a_ph, 1),
+                       "lambda": round(prm.lam, 4), "iterations": prm.iterations,
+                       "flow": "half-size inputs" if half else "full size",
+                       "step_ms_p50": round(float(np.median(ms)), 4),
+                       "step_ms_p99": round(float(np.percentile(ms, 99)), 4),
+                       "frame_ms_p50": round(float(np.median(fms)), 4),
+                       "frames_per_s": round(1e3 / float(np.median(fms)), 2)}
+    fin = res["final"]
     return {
-        "what": "paper Sec. 3.1 Eq. 2-8 at 1920x1080: weights, references, 150 iterations "
-                "(k1 0.3, k2 0.5, a_ph 6500, lambda 2, eta 0.15, kappa 0.2)",
-        "step_ms_p50": round(step_ms, 4),
-        "step_ms_p99": round(float(np.percentile(ms, 99)), 4),
-        "frames_per_s_with_flow": round(1e3 / (step_ms + flow_ms), 2),
+        "what": "paper Sec. 3.1 Eq. 2-8 at 1920x1080: weights, references, momentum iterations "
+                "(eta 0.15, kappa 0.2); presets of Sec. 4.2 (final, objective) and the fast preset "
+                "of Sec. 4.1 (flow on half-size inputs, 50 iterations)",
+        "step_ms_p50": fin["step_ms_p50"],
+        "step_ms_p99": fin["step_ms_p99"],
+        "frames_per_s_with_flow": fin["frames_per_s"],
+        "frame_note": "frame = flow pair (t, t+1) with both pyramids + the step at t, FP32 net, "
+                      "one timed region",
+        "presets": res,
+        "fast_half_flow_epe_vs_full_px": round(half_epe, 4),
+        "fast_vs_final_output_mean_abs": round(float((outs["fast"] - outs["final"]).abs().mean()),
+                                               5),
         "context": "the paper reports 42.7 ms (RTX 3090) / 184.1 ms (GTX 1080Ti) for this stage "
                    "at 1920x1080 (Table: runtime per frame)",
     }

@@ -155,6 +155,23 @@ TC_API int tc_flow_estimate_pair(const tc_net* net, const float* prev, const flo
                                  int h, int w, float* flow_fw, float* flow_bw, void* ws,
                                  size_t ws_bytes, void* stream);
 
+/* Flow pair of the paper's fast preset (Sec. 4.1, implementation details:
+ * optical flow computed on half-sized inputs).  Each frame is reduced to
+ * h2 x w2 = ceil(h/2) x ceil(w/2) by taking the mean of every 2 x 2 pixel
+ * block (a block that runs past the last row or column repeats it), the
+ * pair is estimated at that size as by tc_flow_estimate_pair, and each flow
+ * is brought back to h x w by bilinear upsampling with half-pixel centres
+ * (output pixel i samples the half-size flow at (i + 1/2)/2 - 1/2, clamped
+ * to the half-size grid) times 2.  Arguments as for tc_flow_estimate_pair;
+ * the workspace (caller-owned device memory, 256-byte aligned) must hold
+ * tc_flow_half_workspace_bytes(net, n, h, w).  Errors: TC_ERR_INVALID_ARG
+ * for null pointers or n, h, w < 1, TC_ERR_WORKSPACE for a small or
+ * misaligned workspace. */
+TC_API size_t tc_flow_half_workspace_bytes(const tc_net* net, int n, int h, int w);
+TC_API int tc_flow_estimate_pair_half(const tc_net* net, const float* prev, const float* cur,
+                                      int n, int h, int w, float* flow_fw, float* flow_bw,
+                                      void* ws, size_t ws_bytes, void* stream);
+
 /* ---- consistency step -------------------------------------------------- */
 
 /* out_t from stylized P_t, previous output O_{t-1}, flow_fw = flow(I_{t-1}
@@ -187,6 +204,20 @@ typedef struct {
 } tc_paper_params;
 
 TC_API void tc_paper_default_params(tc_paper_params* p);
+
+/* The paper's parameter presets (Sec. 4.2, parameter settings; Sec. 4.1 for
+ * the fast preset), eta 0.15 and kappa 0.2 in all:
+ *   TC_PRESET_FINAL      k1 0.3, k2 0.5, a_ph 6500, lambda 2, 150 iterations
+ *                        (the setting of its results; = tc_paper_default_params)
+ *   TC_PRESET_OBJECTIVE  k1 = k2 = 0.3, a_ph 10000, lambda 0.7, 150 iterations
+ *                        (tuned for low warping error)
+ *   TC_PRESET_FAST       the final setting with 50 iterations; the paper
+ *                        pairs it with flow on half-sized inputs
+ *                        (tc_flow_estimate_pair_half) and gives no iteration
+ *                        count, 50 is this library's choice.
+ * Returns TC_ERR_INVALID_ARG for a null `p` or an unknown preset. */
+enum { TC_PRESET_FINAL = 0, TC_PRESET_OBJECTIVE = 1, TC_PRESET_FAST = 2 };
+TC_API int tc_paper_preset_params(int preset, tc_paper_params* p);
 TC_API size_t tc_paper_workspace_bytes(int n, int h, int w);
 
 /* O_t of the paper's step.  Inputs n x 3 x h x w: I_{t-1}, I_t, I_{t+1},

@@ -29,6 +29,9 @@ Stylizing Video Streams"):
   fine) with "light" estimators that keep a dense connection only into the
   last layer.
 * Supplementary Eq. S1: the end-point error.
+* Sec. 4.1, implementation details: the fast preset computes the flow on
+  half-sized inputs (2 x 2 block means here) and upsamples it back; Sec. 4.2,
+  parameter settings: the "objective" and final parameter sets.
 * Sec. 3.2, "Optimized Network Architecture", and the supplementary ablation
   of the flow estimators and the refinement: the network variant without the
   estimator of the finest level (its flow, at the next level, is upsampled
@@ -372,6 +375,36 @@ def flow_pair(A, B, wts, desc):
 
 
 # --------------------------------------------------------------------------
+# the paper's fast preset: flow on half-sized inputs (Sec. 4.1)
+
+
+def half_frame(img):
+    """(C, h, w) -> (C, ceil(h/2), ceil(w/2)): the mean of each 2 x 2 pixel
+    block; a block that runs past the last row or column repeats it (the
+    image is extended by edge replication to even size first)."""
+    img = np.asarray(img, np.float64)
+    C, h, w = img.shape
+    ext = np.pad(img, ((0, 0), (0, h % 2), (0, w % 2)), mode="edge")
+    H2, W2 = ext.shape[1] // 2, ext.shape[2] // 2
+    out = np.zeros((C, H2, W2))
+    for dy in (0, 1):
+        for dx in (0, 1):
+            out += ext[:, dy::2, dx::2]
+    return out / 4.0
+
+
+def flow_pair_half(A, B, wts, desc):
+    """Flow pair of the fast preset: both frames halved (half_frame), the
+    pair estimated at that size, each flow upsampled by 2 (bilinear, half-pixel
+    centres), cropped to the input size and multiplied by 2 (one half-size
+    pixel spans two input pixels)."""
+    A = np.asarray(A, np.float64)
+    h, w = A.shape[1:]
+    fa, fb = flow_pair(half_frame(A), half_frame(B), wts, desc)
+    return tuple(2.0 * upsample(f, 2)[:, :h, :w] for f in (fa, fb))
+
+
+# --------------------------------------------------------------------------
 # consistency step
 
 
@@ -440,6 +473,16 @@ def warping_error(Vt, Vt1, flow_t_t1, mask):
 # the paper's full consistency step (Sec. 3.1, Eq. 1-8)
 
 PAPER_DEFAULTS = dict(k1=0.3, k2=0.5, a_ph=6.5e3, lam=2.0, eta=0.15, kappa=0.2, iters=150)
+
+# Sec. 4.2, parameter settings: the final setting (= PAPER_DEFAULTS) and the
+# one tuned for low warping error ("objective"); Sec. 4.1: a fast preset with
+# fewer iterations (no count given; 50 is the reading taken here) used with
+# flow on half-sized inputs (flow_pair_half).
+PAPER_PRESETS = {
+    "final": dict(PAPER_DEFAULTS),
+    "objective": dict(PAPER_DEFAULTS, k1=0.3, k2=0.3, a_ph=10e3, lam=0.7),
+    "fast": dict(PAPER_DEFAULTS, iters=50),
+}
 
 
 def photometric_weight(I, Iw, a_ph):

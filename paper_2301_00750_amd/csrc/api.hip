@@ -935,6 +935,41 @@ int tc_flow_estimate_pair(const tc_net* net, const float* prev, const float* cur
   return flow_common(net, prev, cur, n, h, w, flow_fw, flow_bw, ws, ws_bytes, stream);
 }
 
+size_t tc_flow_half_workspace_bytes(const tc_net* net, int n, int h, int w) {
+  if (!net || !shape_ok(n, h, w)) return 0;
+  const int h2 = (h + 1) / 2, w2 = (w + 1) / 2;
+  const size_t fr = align_up((size_t)n * 3 * h2 * w2 * sizeof(float), kAlign);
+  const size_t fl = align_up((size_t)n * 2 * h2 * w2 * sizeof(float), kAlign);
+  return 2 * fr + 2 * fl + tc_flow_workspace_bytes(net, n, h2, w2);
+}
+
+int tc_flow_estimate_pair_half(const tc_net* net, const float* prev, const float* cur, int n,
+                               int h, int w, float* flow_fw, float* flow_bw, void* ws,
+                               size_t ws_bytes, void* stream) {
+  if (!net || !prev || !cur || !flow_fw || !flow_bw || !ws || !shape_ok(n, h, w))
+    return TC_ERR_INVALID_ARG;
+  if (!aligned(ws) || ws_bytes < tc_flow_half_workspace_bytes(net, n, h, w))
+    return TC_ERR_WORKSPACE;
+  const int h2 = (h + 1) / 2, w2 = (w + 1) / 2;
+  const size_t fr = align_up((size_t)n * 3 * h2 * w2 * sizeof(float), kAlign);
+  const size_t fl = align_up((size_t)n * 2 * h2 * w2 * sizeof(float), kAlign);
+  char* base = static_cast<char*>(ws);
+  float* a2 = reinterpret_cast<float*>(base);
+  float* b2 = reinterpret_cast<float*>(base + fr);
+  float* fw2 = reinterpret_cast<float*>(base + 2 * fr);
+  float* bw2 = reinterpret_cast<float*>(base + 2 * fr + fl);
+  char* rest = base + 2 * fr + 2 * fl;
+  hipStream_t s = (hipStream_t)stream;
+  TC_TRY_HIP(launch_half_frames(prev, 3 * n, h, w, a2, s));
+  TC_TRY_HIP(launch_half_frames(cur, 3 * n, h, w, b2, s));
+  const int st = flow_common(net, a2, b2, n, h2, w2, fw2, bw2, rest,
+                             tc_flow_workspace_bytes(net, n, h2, w2), stream);
+  if (st) return st;
+  TC_TRY_HIP(launch_flow_up2_planes(fw2, n, h2, w2, h, w, flow_fw, s));
+  TC_TRY_HIP(launch_flow_up2_planes(bw2, n, h2, w2, h, w, flow_bw, s));
+  return TC_OK;
+}
+
 int tc_consistency_step(const float* stylized, const float* prev_out, const float* flow_fw,
                         const float* flow_bw, float alpha, int n, int h, int w, float* out,
                         unsigned char* mask_or_null, void* stream) {
@@ -966,6 +1001,26 @@ void tc_paper_default_params(tc_paper_params* p) {
   p->eta = 0.15f;
   p->kappa = 0.2f;
   p->iterations = 150;
+}
+
+int tc_paper_preset_params(int preset, tc_paper_params* p) {
+  if (!p) return TC_ERR_INVALID_ARG;
+  tc_paper_default_params(p);
+  switch (preset) {
+    case TC_PRESET_FINAL:
+      return TC_OK;
+    case TC_PRESET_OBJECTIVE:
+      p->k1 = 0.3f;
+      p->k2 = 0.3f;
+      p->a_ph = 1.0e4f;
+      p->lambda = 0.7f;
+      return TC_OK;
+    case TC_PRESET_FAST:
+      p->iterations = 50;
+      return TC_OK;
+    default:
+      return TC_ERR_INVALID_ARG;
+  }
 }
 
 size_t tc_paper_workspace_bytes(int n, int h, int w) {

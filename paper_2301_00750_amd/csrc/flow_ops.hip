@@ -114,6 +114,50 @@ __global__ __launch_bounds__(256) void final_flow_kernel(const float* __restrict
   }
 }
 
+// Half-size frames: the mean of each 2x2 pixel block of every plane; a block
+// that runs past the last row or column repeats it.
+__global__ __launch_bounds__(256) void half_frames_kernel(const float* __restrict__ in, int planes,
+                                                          int h, int w, int h2, int w2,
+                                                          float* __restrict__ out) {
+  const size_t total = (size_t)planes * h2 * w2;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % w2);
+    const int y = (int)((i / w2) % h2);
+    const size_t p = i / ((size_t)w2 * h2);
+    const float* src = in + p * h * w;
+    const int y0 = 2 * y, y1 = min(2 * y + 1, h - 1), x0 = 2 * x, x1 = min(2 * x + 1, w - 1);
+    out[i] = 0.25f * ((src[(size_t)y0 * w + x0] + src[(size_t)y0 * w + x1]) +
+                      (src[(size_t)y1 * w + x0] + src[(size_t)y1 * w + x1]));
+  }
+}
+
+// Flow (n x 2 x h2 x w2) to n x 2 x H x W: bilinear, half-pixel centres,
+// times 2.
+__global__ __launch_bounds__(256) void flow_up2_planes_kernel(const float* __restrict__ in, int n,
+                                                              int h2, int w2, int H, int W,
+                                                              float* __restrict__ out) {
+  const size_t total = (size_t)n * H * W;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % W);
+    const int y = (int)((i / W) % H);
+    const size_t img = i / ((size_t)W * H);
+    int y0, y1, x0, x1;
+    float fy, fx;
+    up2_taps(y, h2, y0, y1, fy);
+    up2_taps(x, w2, x0, x1, fx);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const float* f = in + (img * 2 + c) * h2 * w2;
+      const float a = f[y0 * w2 + x0], b = f[y0 * w2 + x1], cc = f[y1 * w2 + x0],
+                  d = f[y1 * w2 + x1];
+      out[(img * 2 + c) * H * W + (size_t)y * W + x] =
+          2.f * ((1.f - fy) * ((1.f - fx) * a + fx * b) + fy * ((1.f - fx) * cc + fx * d));
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void flow_to_block_kernel(const float* __restrict__ flow, int n,
                                                             int hw, T* __restrict__ out, int cbt,
@@ -346,6 +390,24 @@ hipError_t launch_final_flow(const float* flow_f, int n, int hf, int wf, int sca
     return hipErrorInvalidValue;
   final_flow_kernel<<<grid_for(total), 256, 0, s>>>(flow_f, n, hf, wf, scale, out_a, out_b, nsplit,
                                                     H, W, out_tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_half_frames(const float* in, int planes, int h, int w, float* out,
+                              hipStream_t s) {
+  const int h2 = (h + 1) / 2, w2 = (w + 1) / 2;
+  const size_t total = (size_t)planes * h2 * w2;
+  if (!total) return hipSuccess;
+  half_frames_kernel<<<grid_for(total), 256, 0, s>>>(in, planes, h, w, h2, w2, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_flow_up2_planes(const float* in, int n, int h2, int w2, int H, int W, float* out,
+                                  hipStream_t s) {
+  const size_t total = (size_t)n * H * W;
+  if (!total) return hipSuccess;
+  if (2L * h2 < H || 2L * w2 < W) return hipErrorInvalidValue;
+  flow_up2_planes_kernel<<<grid_for(total), 256, 0, s>>>(in, n, h2, w2, H, W, out);
   return hipGetLastError();
 }
 

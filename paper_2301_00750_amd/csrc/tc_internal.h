@@ -147,6 +147,13 @@ hipError_t launch_warp_cost_volume(const CvArgs& a, hipStream_t s);
 // Output: flow NCHW (n x 2 x H x W) = crop(s * upsample(flow_f, s)) with
 // s = 2^finest (bilinear, half-pixel centres); flow_f NHWC (n x hf x wf x 2).
 // Images [0, nsplit) go to out_a, the rest to out_b.
+// Fast-preset resampling: 2x2 block means of `planes` h x w planes into
+// ceil(h/2) x ceil(w/2) planes; flow planes (n x 2 x h2 x w2) upsampled to
+// H x W with half-pixel centres and multiplied by 2.
+hipError_t launch_half_frames(const float* in, int planes, int h, int w, float* out,
+                              hipStream_t s);
+hipError_t launch_flow_up2_planes(const float* in, int n, int h2, int w2, int H, int W, float* out,
+                                  hipStream_t s);
 hipError_t launch_final_flow(const float* flow_f, int n, int hf, int wf, int scale, float* out_a,
                              float* out_b, int nsplit, int H, int W, float* const* out_tab,
                              hipStream_t s);

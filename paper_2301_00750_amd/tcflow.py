@@ -28,7 +28,11 @@ EXPORTS = (
     "tc_fp8_e4m3_encode", "tc_decoder_list_workspace_bytes", "tc_flow_from_pyramid_list",
     "tc_train_default_params", "tc_trainer_create", "tc_trainer_destroy", "tc_trainer_grad",
     "tc_trainer_step", "tc_trainer_copy", "tc_trainer_steps_done", "tc_flow_agreement",
+    "tc_flow_half_workspace_bytes", "tc_flow_estimate_pair_half", "tc_paper_preset_params",
 )
+
+TC_PRESET_FINAL, TC_PRESET_OBJECTIVE, TC_PRESET_FAST = 0, 1, 2
+PRESETS = {"final": TC_PRESET_FINAL, "objective": TC_PRESET_OBJECTIVE, "fast": TC_PRESET_FAST}
 
 (TC_OP_PYR_A, TC_OP_PYR_B, TC_OP_UP2, TC_OP_COST_VOLUME, TC_OP_C1, TC_OP_C2, TC_OP_C3, TC_OP_HEAD,
  TC_OP_REFINE) = range(9)
@@ -123,6 +127,9 @@ def _load():
         "tc_trainer_copy": (ci, [vp, ci, vp, vp]),
         "tc_trainer_steps_done": (ci, [vp]),
         "tc_flow_agreement": (ci, [vp, vp, ci, ci, ci, vp, vp]),
+        "tc_flow_half_workspace_bytes": (sz, [vp, ci, ci, ci]),
+        "tc_flow_estimate_pair_half": (ci, [vp, vp, vp, ci, ci, ci, vp, vp, vp, sz, vp]),
+        "tc_paper_preset_params": (ci, [ci, ctypes.POINTER(PaperParams)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -237,6 +244,26 @@ class Net:
             n, h, w, arr(*[f.data_ptr() for f in fw]), arr(*[f.data_ptr() for f in bw]), _ptr(ws),
             ws.numel() * ws.element_size(), _stream(stream)))
 
+    def flow_half_workspace_bytes(self, n, h, w):
+        return _lib.tc_flow_half_workspace_bytes(self._h, n, h, w)
+
+    def flow_estimate_pair_half(self, prev, cur, ws=None, out_fw=None, out_bw=None, stream=None):
+        """Flow pair of the fast preset: estimated on 2x2-block-mean half-size
+        frames, upsampled back (tc_flow_estimate_pair_half)."""
+        _frames(prev, "prev", 3)
+        _frames(cur, "cur", 3)
+        if prev.shape != cur.shape:
+            raise ValueError("prev and cur differ in shape")
+        n, _, h, w = prev.shape
+        if ws is None:
+            ws = _workspace(self.flow_half_workspace_bytes(n, h, w), prev.device)
+        fw = out_fw if out_fw is not None else torch.empty(n, 2, h, w, device=prev.device)
+        bw = out_bw if out_bw is not None else torch.empty(n, 2, h, w, device=prev.device)
+        _check("tc_flow_estimate_pair_half", _lib.tc_flow_estimate_pair_half(
+            self._h, _ptr(prev), _ptr(cur), n, h, w, _ptr(fw), _ptr(bw), _ptr(ws),
+            ws.numel() * ws.element_size(), _stream(stream)))
+        return fw, bw
+
     def flow_estimate(self, prev, cur, ws=None, out=None, stream=None):
         _frames(prev, "prev", 3)
         _frames(cur, "cur", 3)
@@ -305,6 +332,16 @@ def paper_params(**kw):
     (k1, k2, a_ph, lam, eta, kappa, iterations)."""
     p = PaperParams()
     _lib.tc_paper_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def paper_preset(name, **kw):
+    """The paper's parameter preset `name` ("final", "objective", "fast";
+    tc_paper_preset_params), with keyword overrides."""
+    p = PaperParams()
+    _check("tc_paper_preset_params", _lib.tc_paper_preset_params(PRESETS[name], ctypes.byref(p)))
     for k, v in kw.items():
         setattr(p, k, v)
     return p

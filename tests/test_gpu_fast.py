@@ -1,0 +1,109 @@
+"""GPU parity of the paper's fast preset and parameter presets (Sec. 4.1,
+implementation details; Sec. 4.2, parameter settings) through the C ABI
+against the FP64 oracle.
+
+* tc_flow_estimate_pair_half: flows from half-size inputs, upsampled back,
+  against oracle.flow_pair_half; even and odd sizes (the odd ones repeat the
+  last row / column in the 2 x 2 means and crop the upsampled flow).  FP32
+  bar: max EPE 4e-3 px (the full-size FP32 bar of 2e-3 px, doubled with the
+  flow); BF16: mean EPE 0.25 px.
+* tc_consistency_paper with the "objective" and "fast" presets: 1e-4 on
+  values in [0, 1], as for the final setting (the objective preset's larger
+  a_ph = 1e4 scales a float32 rounding of the photometric distance by at
+  most 1e4 * 1e-7 = 1e-3 of a weight, still far below the bar after the
+  blend).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import tcflow_oracle as O
+from paper_2301_00750_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tc():
+    from paper_2301_00750_amd import tcflow
+    assert torch.cuda.is_available()
+    return tcflow
+
+
+def f64(t):
+    return t.detach().cpu().double().numpy()
+
+
+def epe(a, b):
+    e = np.sqrt(((f64(a) - b) ** 2).sum(0))
+    return e.mean(), e.max()
+
+
+@pytest.mark.parametrize("hw,prec", [((96, 128), "fp32"), ((97, 131), "fp32"), ((33, 47), "fp32"),
+                                     ((97, 131), "bf16")])
+def test_half_flow_pair_vs_oracle(tc, hw, prec):
+    d = synth.load_desc("tiny")
+    blob = synth.he_weights(d)
+    net = tc.Net(d, blob, precision=tc.TC_FP32 if prec == "fp32" else tc.TC_BF16)
+    sc = synth.LayeredScene(hw[1], hw[0], seed=21, max_shift=4.0)
+    A, B = sc.frame(0), sc.frame(1)
+    say(f"[fast] half-size flow pair {hw} {prec}")
+    fw, bw = net.flow_estimate_pair_half(A[None].cuda(), B[None].cuda())
+    torch.cuda.synchronize()
+    assert fw.shape == (1, 2) + hw
+    rfw, rbw = O.flow_pair_half(f64(A), f64(B), O.unpack_weights(blob, d), d)
+    for a, b in ((fw[0], rfw), (bw[0], rbw)):
+        mean, mx = epe(a, b)
+        say(f"   EPE mean={mean:.3e} max={mx:.3e}")
+        if prec == "fp32":
+            assert mx <= 4e-3
+        else:
+            assert mean <= 0.25
+
+
+def test_half_flow_pair_batch_equals_single(tc):
+    d = synth.load_desc("tiny")
+    net = tc.Net(d, synth.he_weights(d))
+    gen = torch.Generator().manual_seed(4)
+    A = torch.rand(3, 3, 50, 70, generator=gen).cuda()
+    B = torch.rand(3, 3, 50, 70, generator=gen).cuda()
+    say("[fast] half-size flow pair, batch of 3 vs one by one")
+    fw, bw = net.flow_estimate_pair_half(A, B)
+    for i in range(3):
+        f1, b1 = net.flow_estimate_pair_half(A[i:i + 1].contiguous(), B[i:i + 1].contiguous())
+        assert torch.equal(fw[i], f1[0]) and torch.equal(bw[i], b1[0])
+
+
+def paper_inputs(h, w, seed):
+    sc = synth.LayeredScene(w, h, seed=seed, max_shift=4.0)
+    I = [sc.frame(t) for t in range(3)]
+    P = [synth.stylize(x, t) for t, x in enumerate(I)]
+    O_prev = synth.stylize(I[0], 7)
+    f_tp, _ = sc.gt_flow(1, 0)
+    f_tn, _ = sc.gt_flow(1, 2)
+    return I, P, O_prev, f_tp, f_tn
+
+
+@pytest.mark.parametrize("preset", ["objective", "fast"])
+def test_paper_presets_vs_oracle(tc, preset):
+    h, w = 96, 128
+    I, P, Op, f_tp, f_tn = paper_inputs(h, w, 13)
+    say(f"[fast] paper step, preset {preset}")
+    prm = tc.paper_preset(preset)
+    c = lambda t: t[None].cuda().contiguous()  # noqa: E731
+    out = tc.consistency_paper(c(I[0]), c(I[1]), c(I[2]), c(P[0]), c(P[1]), c(P[2]), c(Op),
+                               c(f_tp), c(f_tn), prm)
+    torch.cuda.synchronize()
+    ref, _, _ = O.paper_consistency(f64(I[0]), f64(I[1]), f64(I[2]), f64(P[0]), f64(P[1]),
+                                    f64(P[2]), f64(Op), f64(f_tp), f64(f_tn),
+                                    O.PAPER_PRESETS[preset])
+    err = np.abs(f64(out[0]) - ref).max()
+    say(f"   max |GPU - oracle| = {err:.2e}")
+    assert err <= 1e-4

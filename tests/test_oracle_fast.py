@@ -1,0 +1,148 @@
+"""Pins of the oracle's fast preset and parameter presets (paper Sec. 4.1,
+implementation details; Sec. 4.2, parameter settings).
+
+* half_frame: closed forms (constants, linear ramps at the block centres,
+  the repeated last row / column of odd sizes) and a brute-force loop that
+  clamps indices instead of padding;
+* flow_pair_half: with the network replaced by a stub that returns a known
+  flow field, the composition (halved inputs, 2x upsampling with half-pixel
+  centres, crop, factor 2) gives the closed-form result;
+* presets: the values the paper prints (tests/golden/paper_parameter_presets.json),
+  in the oracle and in the library's host-side preset call.
+CPU only.
+"""
+import ctypes
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import tcflow_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+RNG = np.random.default_rng(65)
+
+
+@pytest.mark.parametrize("hw", [(6, 8), (7, 9), (1, 1), (1, 5), (3, 1)])
+def test_half_frame_constant(hw):
+    x = np.full((3,) + hw, 0.37)
+    y = O.half_frame(x)
+    assert y.shape == (3, (hw[0] + 1) // 2, (hw[1] + 1) // 2)
+    assert np.allclose(y, 0.37, rtol=0, atol=1e-15)
+
+
+def test_half_frame_ramp_even():
+    """A linear ramp a y + b x + c averages to its value at the block centre
+    (2 i + 1/2, 2 j + 1/2)."""
+    h, w, a, b, c = 10, 14, 0.3, -0.7, 2.0
+    yy, xx = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    y = O.half_frame((a * yy + b * xx + c)[None])[0]
+    ii, jj = np.meshgrid(np.arange(h // 2), np.arange(w // 2), indexing="ij")
+    assert np.allclose(y, a * (2 * ii + 0.5) + b * (2 * jj + 0.5) + c, rtol=0, atol=1e-12)
+
+
+def test_half_frame_odd_repeats_last_row_and_column():
+    h, w, a, b = 7, 9, 1.5, 0.25
+    yy, xx = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    y = O.half_frame((a * yy + b * xx)[None])[0]
+    assert y.shape == (4, 5)
+    # last block row holds row h-1 twice, last block column holds column w-1 twice
+    assert np.allclose(y[3, :4], a * (h - 1) + b * (2 * np.arange(4) + 0.5), atol=1e-12)
+    assert np.allclose(y[:3, 4], a * (2 * np.arange(3) + 0.5) + b * (w - 1), atol=1e-12)
+    assert abs(y[3, 4] - (a * (h - 1) + b * (w - 1))) <= 1e-12
+
+
+def test_half_frame_brute_force():
+    img = RNG.standard_normal((2, 5, 7))
+    out = O.half_frame(img)
+    for c in range(2):
+        for i in range(3):
+            for j in range(4):
+                acc = 0.0
+                for dy in (0, 1):
+                    for dx in (0, 1):
+                        acc += img[c, min(2 * i + dy, 4), min(2 * j + dx, 6)]
+                assert abs(out[c, i, j] - acc / 4) <= 1e-14
+
+
+@pytest.mark.parametrize("hw", [(12, 16), (13, 17)])
+def test_flow_pair_half_composition(monkeypatch, hw):
+    """Stub network: flow = an affine field of the half-size pixel centre.
+    Bilinear upsampling reproduces an affine field exactly wherever no clamp
+    acts, so the output there is 2 x the field at (x + 1/2)/2 - 1/2."""
+    h, w = hw
+    seen = []
+    p, q, r = 0.2, -0.1, 1.5
+
+    def fake_pair(A, B, wts, desc):
+        seen.append((A.shape, B.shape))
+        H2, W2 = A.shape[1:]
+        yy, xx = np.meshgrid(np.arange(H2), np.arange(W2), indexing="ij")
+        f = np.stack([p * xx + q * yy + r, -q * xx + p * yy - r])
+        return f, -f
+
+    monkeypatch.setattr(O, "flow_pair", fake_pair)
+    A = RNG.random((3, h, w))
+    fw, bw = O.flow_pair_half(A, A, None, None)
+    h2, w2 = (h + 1) // 2, (w + 1) // 2
+    assert seen == [((3, h2, w2), (3, h2, w2))]
+    assert fw.shape == bw.shape == (2, h, w)
+    assert np.array_equal(bw, -fw)
+    Y, X = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    sy, sx = (Y + 0.5) / 2 - 0.5, (X + 0.5) / 2 - 0.5
+    inside = (sy >= 0) & (sy <= h2 - 1) & (sx >= 0) & (sx <= w2 - 1)
+    ref = 2 * np.stack([p * sx + q * sy + r, -q * sx + p * sy - r])
+    assert inside.sum() > 0.5 * h * w
+    assert np.allclose(fw[:, inside], ref[:, inside], rtol=0, atol=1e-12)
+
+
+def test_flow_pair_half_constant_flow_doubles(monkeypatch):
+    monkeypatch.setattr(O, "flow_pair", lambda A, B, wts, desc: (
+        np.stack([np.full(A.shape[1:], 1.25), np.full(A.shape[1:], -0.5)]),) * 2)
+    fw, _ = O.flow_pair_half(RNG.random((3, 9, 11)), RNG.random((3, 9, 11)), None, None)
+    assert np.allclose(fw[0], 2.5, atol=1e-14) and np.allclose(fw[1], -1.0, atol=1e-14)
+
+
+def golden():
+    with open(os.path.join(ROOT, "tests", "golden", "paper_parameter_presets.json")) as f:
+        return json.load(f)
+
+
+def test_oracle_presets_match_paper():
+    g = golden()
+    for name in ("objective", "final"):
+        for k, v in g[name].items():
+            assert O.PAPER_PRESETS[name][k] == pytest.approx(v, rel=0, abs=0)
+    for name in ("objective", "final", "fast"):
+        assert O.PAPER_PRESETS[name]["eta"] == g["solver"]["eta"]
+        assert O.PAPER_PRESETS[name]["kappa"] == g["solver"]["kappa"]
+    assert O.PAPER_PRESETS["final"]["iters"] == g["solver"]["iterations"]
+    assert O.PAPER_PRESETS["objective"]["iters"] == g["solver"]["iterations"]
+    # fast: the final setting with fewer iterations (the reading: 50)
+    fast = dict(O.PAPER_PRESETS["fast"])
+    assert fast.pop("iters") == 50
+    final = dict(O.PAPER_PRESETS["final"])
+    final.pop("iters")
+    assert fast == final
+
+
+def test_library_presets_match_paper():
+    from paper_2301_00750_amd import build_lib
+    if not os.path.exists(build_lib.LIB):
+        build_lib.build()
+    from paper_2301_00750_amd import tcflow
+    g = golden()
+    for name, want_iters in (("objective", 150), ("final", 150), ("fast", 50)):
+        p = tcflow.paper_preset(name)
+        src = g["final"] if name == "fast" else g[name]
+        assert p.k1 == pytest.approx(src["k1"], rel=1e-7)
+        assert p.k2 == pytest.approx(src["k2"], rel=1e-7)
+        assert p.a_ph == pytest.approx(src["a_ph"], rel=1e-7)
+        assert p.lam == pytest.approx(src["lam"], rel=1e-7)
+        assert p.eta == pytest.approx(g["solver"]["eta"], rel=1e-7)
+        assert p.kappa == pytest.approx(g["solver"]["kappa"], rel=1e-7)
+        assert p.iterations == want_iters
+    bad = tcflow.PaperParams()
+    assert tcflow.lib().tc_paper_preset_params(7, ctypes.byref(bad)) == tcflow.TC_ERR_INVALID_ARG
+    assert tcflow.lib().tc_paper_preset_params(0, None) == tcflow.TC_ERR_INVALID_ARG
