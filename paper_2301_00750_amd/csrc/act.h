@@ -11,6 +11,15 @@ typedef unsigned short bf16;  // storage type of bfloat16 activations
 
 __device__ inline float bf2f(bf16 h) { return __uint_as_float((unsigned)h << 16); }
 
+// Load through the global address space (global_load_*).  Pointers picked
+// from views or device tables are generic, and generic (flat) loads also
+// count against the LDS wait counter: every wait for an LDS read would then
+// wait for the prefetch of the next chunk as well.
+template <typename T>
+__device__ inline T ldg(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float float2v __attribute__((ext_vector_type(2)));
 
@@ -30,6 +39,21 @@ __device__ inline void load8(const float* p, float (&v)[8]) {
 
 __device__ inline void load8(const bf16* p, float (&v)[8]) {
   const u4 x = *reinterpret_cast<const u4*>(p);
+  v[0] = __uint_as_float(x.x << 16); v[1] = __uint_as_float(x.x & 0xffff0000u);
+  v[2] = __uint_as_float(x.y << 16); v[3] = __uint_as_float(x.y & 0xffff0000u);
+  v[4] = __uint_as_float(x.z << 16); v[5] = __uint_as_float(x.z & 0xffff0000u);
+  v[6] = __uint_as_float(x.w << 16); v[7] = __uint_as_float(x.w & 0xffff0000u);
+}
+
+// load8 from global memory (see ldg)
+__device__ inline void load8g(const float* p, float (&v)[8]) {
+  const f4 a = ldg(reinterpret_cast<const f4*>(p)), b = ldg(reinterpret_cast<const f4*>(p) + 1);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+__device__ inline void load8g(const bf16* p, float (&v)[8]) {
+  const u4 x = ldg(reinterpret_cast<const u4*>(p));
   v[0] = __uint_as_float(x.x << 16); v[1] = __uint_as_float(x.x & 0xffff0000u);
   v[2] = __uint_as_float(x.y << 16); v[3] = __uint_as_float(x.y & 0xffff0000u);
   v[4] = __uint_as_float(x.z << 16); v[5] = __uint_as_float(x.z & 0xffff0000u);

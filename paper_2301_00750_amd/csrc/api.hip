@@ -416,7 +416,11 @@ int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, in
     const ConvPlan p = plan_conv(out_h, out_w, n, a.nchunks, stride, L.np);
     a.splits = p.splits;
     a.cps = p.cps;
-    e = launch_conv3x3(a, stride, L.kc, p.mr, s);
+    // large FP32 stride-1 layers: Winograd F(2x2, 3x3) on the matrix cores
+    if (L.wu && p.mr == 4 && p.splits == 1 && wino_ok(a, stride, L.kc))
+      e = launch_conv3x3_wino(a, L.wu, s);
+    else
+      e = launch_conv3x3(a, stride, L.kc, p.mr, s);
   }
   probe_end(stage, s);
   return e == hipSuccess ? TC_OK : TC_ERR_HIP;
@@ -667,6 +671,7 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     std::vector<char> w;
     std::vector<float> b;
     std::vector<float> sc;  // FP8 per-output-channel weight scales
+    std::vector<float> wu;  // Winograd-transformed weights (FP32 stride-1 layers)
   };
   std::vector<Packed> packed;
   std::vector<ConvLayer*> slots;
@@ -676,7 +681,7 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
   // coarse levels, whose errors are amplified by every upsampling on the way
   // to full resolution, stay BF16.
   auto add_layer = [&](ConvLayer& cl, int cout, int cin, int kc, int cin_pad,
-                       const std::vector<int>& cmap, bool head, bool fp8_ok) {
+                       const std::vector<int>& cmap, bool head, bool fp8_ok, bool stride1) {
     const float* W = src;
     const float* b = src + (size_t)cout * cin * 9;
     src += conv_floats(cout, cin);
@@ -700,6 +705,8 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
       pack_conv(W, b, cout, cin, kc, cin_pad, cmap, wf, pk.b, np);
       pk.w.resize(wf.size() * 4);
       memcpy(pk.w.data(), wf.data(), pk.w.size());
+      if (stride1 && !head && kc == 8 && cout % 32 == 0)
+        pack_conv_wino(W, cout, cin, cin_pad, cmap, pk.wu);
     }
     cl.cin = cin;
     cl.cout = cout;
@@ -720,8 +727,8 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     // the staged frame is one block of 4 (float) or 8 (bfloat16) channels
     const int kc = (l == 1 && !net->bf16act) ? 4 : 8;
     const int pad = l == 1 ? kc : cin;
-    add_layer(net->pyr[l - 1][0], C, cin, kc, pad, identity(cin, pad), false, false);
-    add_layer(net->pyr[l - 1][1], C, C, 8, C, identity(C, C), false, false);
+    add_layer(net->pyr[l - 1][0], C, cin, kc, pad, identity(cin, pad), false, false, false);
+    add_layer(net->pyr[l - 1][1], C, C, 8, C, identity(C, C), false, false, true);
   }
   const int d0 = desc->dec[0], d1 = desc->dec[1], d2 = desc->dec[2];
   for (int l = desc->finest; l <= L; ++l) {
@@ -735,10 +742,11 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     m[C + net->ncv] = net->ncv + C;
     m[C + net->ncv + 1] = net->ncv + C + 1;
     const bool f8 = l <= 2;
-    add_layer(net->dec[l - 1][0], d0, net->ncv + C + 2, 8, pad, m, false, f8);
-    add_layer(net->dec[l - 1][1], d1, d0, 8, d0, identity(d0, d0), false, f8);
-    add_layer(net->dec[l - 1][2], d2, d1, 8, d1, identity(d1, d1), false, f8);
-    add_layer(net->dec[l - 1][3], 2, d1 + d2, 8, d1 + d2, identity(d1 + d2, d1 + d2), true, false);
+    add_layer(net->dec[l - 1][0], d0, net->ncv + C + 2, 8, pad, m, false, f8, true);
+    add_layer(net->dec[l - 1][1], d1, d0, 8, d0, identity(d0, d0), false, f8, true);
+    add_layer(net->dec[l - 1][2], d2, d1, 8, d1, identity(d1, d1), false, f8, true);
+    add_layer(net->dec[l - 1][3], 2, d1 + d2, 8, d1 + d2, identity(d1 + d2, d1 + d2), true, false,
+              true);
   }
 
   // refinement: per layer the pointwise weights packed as the sepconv kernel
@@ -774,6 +782,8 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     total = align_up(total + pk.w.size(), kAlign);
     offs.push_back(total);
     total = align_up(total + (pk.b.size() + pk.sc.size()) * sizeof(float), kAlign);
+    offs.push_back(total);
+    total = align_up(total + pk.wu.size() * sizeof(float), kAlign);
   }
   for (auto& sp : sep) {
     offs.push_back(total);
@@ -787,17 +797,22 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
   }
   std::vector<char> host(total, 0);
   for (size_t i = 0; i < packed.size(); ++i) {
-    memcpy(host.data() + offs[2 * i], packed[i].w.data(), packed[i].w.size());
-    memcpy(host.data() + offs[2 * i + 1], packed[i].b.data(), packed[i].b.size() * sizeof(float));
+    memcpy(host.data() + offs[3 * i], packed[i].w.data(), packed[i].w.size());
+    memcpy(host.data() + offs[3 * i + 1], packed[i].b.data(), packed[i].b.size() * sizeof(float));
     if (!packed[i].sc.empty())
-      memcpy(host.data() + offs[2 * i + 1] + packed[i].b.size() * sizeof(float),
+      memcpy(host.data() + offs[3 * i + 1] + packed[i].b.size() * sizeof(float),
              packed[i].sc.data(), packed[i].sc.size() * sizeof(float));
-    slots[i]->w = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[2 * i]);
-    slots[i]->b = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[2 * i + 1]);
+    if (!packed[i].wu.empty())
+      memcpy(host.data() + offs[3 * i + 2], packed[i].wu.data(), packed[i].wu.size() * sizeof(float));
+    slots[i]->w = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[3 * i]);
+    slots[i]->b = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[3 * i + 1]);
     if (slots[i]->fp8) slots[i]->ws = slots[i]->b + packed[i].b.size();
+    slots[i]->wu = packed[i].wu.empty()
+                       ? nullptr
+                       : reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[3 * i + 2]);
   }
   for (size_t j = 0; j < sep.size(); ++j) {
-    const size_t o0 = offs[2 * packed.size() + 2 * j], o1 = offs[2 * packed.size() + 2 * j + 1];
+    const size_t o0 = offs[3 * packed.size() + 2 * j], o1 = offs[3 * packed.size() + 2 * j + 1];
     memcpy(host.data() + o0, sep[j].pw.data(), sep[j].pw.size());
     memcpy(host.data() + o1, sep[j].rest.data(), sep[j].rest.size() * sizeof(float));
     SepLayer& sl = net->ref[j];

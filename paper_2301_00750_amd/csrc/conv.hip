@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_mfma(ConvArgs a) {
         const int py = pos / IW, px = pos - py * IW;
         const int gy = iy0 + py, gx = ix0 + px;
         if (gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w)
-          val = *reinterpret_cast<const f4*>(src + ((size_t)gy * a.in_w + gx) * KC + c4 * 4);
+          val = ldg(reinterpret_cast<const f4*>(src + ((size_t)gy * a.in_w + gx) * KC + c4 * 4));
       }
       ra[j] = val;
     }
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
         f4 lo = f4{0.f, 0.f, 0.f, 0.f}, hi = lo;
         if (gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w) {
           float vv[8];
-          load8(src + ((size_t)gy * a.in_w + gx) * 8, vv);
+          load8g(src + ((size_t)gy * a.in_w + gx) * 8, vv);
           lo = f4{vv[0], vv[1], vv[2], vv[3]};
           hi = f4{vv[4], vv[5], vv[6], vv[7]};
         }
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
       if (f_off[j] >= 0 && b < nblk) {
         const bf16* src = b < a.nb0 ? base0 + (size_t)(b + a.in0.cb0) * in_plane
                                     : base1 + (size_t)(b - a.nb0 + a.in1.cb0) * in_plane;
-        val = *reinterpret_cast<const u4*>(src + (size_t)f_off[j] * 8);
+        val = ldg(reinterpret_cast<const u4*>(src + (size_t)f_off[j] * 8));
       }
       ra[j] = val;
     }

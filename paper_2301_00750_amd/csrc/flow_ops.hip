@@ -223,11 +223,11 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
       if (Y >= 0 && Y < h && X >= 0 && X < w) {
         if (!U) {
           float v[8];
-          load8(f2c + ((size_t)Y * w + X) * 8, v);
+          load8g(f2c + ((size_t)Y * w + X) * 8, v);
           lo = f4{v[0], v[1], v[2], v[3]};
           hi = f4{v[4], v[5], v[6], v[7]};
         } else {
-          const float2 u = U[(size_t)Y * w + X];
+          const float2v u = ldg(reinterpret_cast<const float2v*>(U + (size_t)Y * w + X));
           const float fx = floorf(u.x), fy = floorf(u.y);
           const float ax = u.x - fx, ay = u.y - fy;
           const int x0 = X + (int)fx, y0 = Y + (int)fy;
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
             const float wt = ((t & 1) ? ax : 1.f - ax) * ((t >> 1) ? ay : 1.f - ay);
             if (xi >= 0 && xi < w && yi >= 0 && yi < h) {
               float v[8];
-              load8(f2c + ((size_t)yi * w + xi) * 8, v);
+              load8g(f2c + ((size_t)yi * w + xi) * 8, v);
               lo += wt * f4{v[0], v[1], v[2], v[3]};
               hi += wt * f4{v[4], v[5], v[6], v[7]};
             }
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
     __syncthreads();
     if (valid) {
       float v1[8];
-      load8(f1 + (size_t)cb * plane + ((size_t)y * w + x) * 8, v1);
+      load8g(f1 + (size_t)cb * plane + ((size_t)y * w + x) * 8, v1);
       const f4 a0 = f4{v1[0], v1[1], v1[2], v1[3]}, a1 = f4{v1[4], v1[5], v1[6], v1[7]};
 #pragma unroll
       for (int dy = 0; dy < D; ++dy)

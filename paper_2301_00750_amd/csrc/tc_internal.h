@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace tc {
 
 constexpr int kBlock = 256;
@@ -54,6 +56,7 @@ struct ConvLayer {
                    // [cdiv(cin_pad / 8, BF_CPC)][BF_STEPS][4][np][8] bfloat16
   int fp8;         // same order, FP8 E4M3 bytes, scaled per output channel by ws
   float* ws;       // device, np per-output-channel weight scales (FP8 layers)
+  float* wu;       // device, Winograd-transformed weights (pack_conv_wino), or null
 };
 
 // Per-image absolute-maximum slots (float bits as unsigned) of an activation
@@ -102,9 +105,17 @@ ConvPlan plan_conv(int out_h, int out_w, int n, int nchunks, int stride, int np)
 size_t conv_partial_bytes(const ConvPlan& p, int out_h, int out_w, int n, int np);
 
 hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, int mr, hipStream_t s);
+// FP32 stride-1 3x3 conv by Winograd F(2x2, 3x3) on the matrix cores
+// (wino.hip): blocked outputs without `add`, cout a multiple of 8, np a
+// multiple of 32, no split K.
+bool wino_ok(const ConvArgs& a, int stride, int kc);
+hipError_t launch_conv3x3_wino(const ConvArgs& a, const float* wu, hipStream_t s);
 // 3x3 conv with two output channels (the estimator head) on vector ALUs,
 // FP32 activations.
 hipError_t launch_head(const ConvArgs& a, hipStream_t s);
+// Host: the weights of launch_conv3x3_wino (G g G^T per channel pair).
+void pack_conv_wino(const float* W, int cout, int cin, int cin_pad, const std::vector<int>& cmap,
+                    std::vector<float>& out);
 
 
 // NCHW float frames (n x 3 x h x w) -> one channel block per pixel, bottom /

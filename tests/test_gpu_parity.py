@@ -290,6 +290,27 @@ def test_fullhd_pair_vs_oracle(tc):
         assert mean <= 0.05 and mx <= 0.05
 
 
+def test_fp32_winograd_levels_ragged_vs_oracle(tc):
+    """Frames of 1040 x 1680 through the 4-level net: levels 1 (520 x 840) and
+    2 (260 x 420) run their stride-1 convs by Winograd F(2x2, 3x3), with
+    tiles cut by the image edge on both axes (520 = 32 * 16 + 8, 260 = 16 *
+    16 + 4).  Same bar as the FP32 full-HD pair."""
+    d = synth.load_desc("tiny")
+    blob = synth.he_weights(d)
+    wts = O.unpack_weights(blob, d)
+    net = tc.Net(d, blob)
+    sc = synth.LayeredScene(1680, 1040, seed=3)
+    I0, I1 = sc.frame(0), sc.frame(1)
+    say("[flow] 1040x1680 pair, 4 levels (Winograd levels 1-2)")
+    fw, bw = net.flow_estimate_pair(g(I0[None]), g(I1[None]))
+    torch.cuda.synchronize()
+    rfw, rbw = O.flow_pair(f64(I0), f64(I1), wts, d)
+    for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
+        mean, mx = flow_err(a, b)
+        say(f"   {name}: EPE mean={mean:.3e} max={mx:.3e}")
+        assert mean <= 0.05 and mx <= 0.05
+
+
 # ---------------------------------------------------------------- BF16 precision form
 #
 # Convolutions and the cost volume read BF16 activations and weights and
