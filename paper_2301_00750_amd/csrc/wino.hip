@@ -38,9 +38,13 @@ namespace {
 constexpr int WT = 16;             // output tile edge
 constexpr int WI = WT + 2;         // input halo edge
 constexpr int WNPOS = WI * WI;     // 324 halo pixels
-// LDS pitch of a channel plane: 4 planes apart = 16 mod 32 banks, so the two
-// lanes that store channels c and c + 4 of one pixel hit different banks
-constexpr int WAP = 372;
+// LDS layout of a staged channel plane: halo rows padded to WRP = 24 floats,
+// so the two tile rows a group of 16 lanes reads (2 halo rows apart, 48 =
+// 16 mod 32) fall on disjoint banks; planes WAP = 436 floats apart (4 planes
+// = 16 mod 32), so the lanes that store channels c and c + 4 of one pixel do
+// not collide.
+constexpr int WRP = 24;
+constexpr int WAP = 436;
 constexpr int WNA = WNPOS * 2;     // float4 of input per chunk (8 channels)
 constexpr int WRA = (WNA + 255) / 256;
 constexpr int WUF = 16 * 2 * 64 * 2;  // transformed weights per chunk and slice
@@ -123,10 +127,11 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_wino(ConvArgs a, const flo
       if (i < WNA) {
         const int pos = i >> 1, c4 = i & 1;
         const f4 val = ((inb >> j) & 1u) ? ra[j] : f4{0.f, 0.f, 0.f, 0.f};
-        st[(c4 * 4 + 0) * WAP + pos] = val.x;
-        st[(c4 * 4 + 1) * WAP + pos] = val.y;
-        st[(c4 * 4 + 2) * WAP + pos] = val.z;
-        st[(c4 * 4 + 3) * WAP + pos] = val.w;
+        const int py = pos / WI, lp = py * WRP + (pos - py * WI);
+        st[(c4 * 4 + 0) * WAP + lp] = val.x;
+        st[(c4 * 4 + 1) * WAP + lp] = val.y;
+        st[(c4 * 4 + 2) * WAP + lp] = val.z;
+        st[(c4 * 4 + 3) * WAP + lp] = val.w;
       }
     }
 #pragma unroll
@@ -134,15 +139,15 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_wino(ConvArgs a, const flo
   };
 
   // this lane's Winograd tile (A row m = lm): tile row 2 * wave + lm / 8, column lm % 8
-  const int aoff = 2 * (2 * wave + (lm >> 3)) * WI + 2 * (lm & 7);
+  const int aoff = 2 * (2 * wave + (lm >> 3)) * WRP + 2 * (lm & 7);
 
   // the 4x4 patch of channel c of the lane's tile, and its transform B^T d B
   auto read_patch = [&](const float* st, int c, float (&d)[16]) {
     const float* s = st + c * WAP + aoff;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float2 lo = *reinterpret_cast<const float2*>(s + i * WI);
-      const float2 hi = *reinterpret_cast<const float2*>(s + i * WI + 2);
+      const float2 lo = *reinterpret_cast<const float2*>(s + i * WRP);
+      const float2 hi = *reinterpret_cast<const float2*>(s + i * WRP + 2);
       d[4 * i + 0] = lo.x;
       d[4 * i + 1] = lo.y;
       d[4 * i + 2] = hi.x;
