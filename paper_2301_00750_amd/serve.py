@@ -79,6 +79,19 @@ class _Slot:
         return 2 * net.pyramid_bytes(1, h, w) + (2 * 3 + 2 * 2 + (6 if staging else 0)) * h * w * 4
 
 
+_GROUP_STREAMS = {}
+
+
+def _group_stream(device, hw):
+    """One HIP stream per (device, resolution), shared by every Server:
+    streams are spread over a few hardware queues in creation order, so
+    creating new ones per server would crowd queues that other work uses."""
+    key = (device.index if device.index is not None else torch.cuda.current_device(), hw)
+    if key not in _GROUP_STREAMS:
+        _GROUP_STREAMS[key] = torch.cuda.Stream(device=device)
+    return _GROUP_STREAMS[key]
+
+
 class Server:
     """Continuous-batching server over one net.
 
@@ -105,7 +118,7 @@ class Server:
     def _group(self, hw):
         g = self.groups.get(hw)
         if g is None:
-            st = torch.cuda.Stream(device=self.device)
+            st = _group_stream(self.device, hw)
             wb = self.group_bytes(hw)
             with torch.cuda.stream(st):  # memory is tied to the stream that uses it
                 ws = torch.empty(wb, dtype=torch.uint8, device=self.device)

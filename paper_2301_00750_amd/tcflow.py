@@ -385,6 +385,22 @@ class Probe:
         _lib.tc_probe_disable()
 
 
+_PIPELINE_STREAMS = {}
+
+
+def _pipeline_streams(device):
+    """The side streams of the pipelined driver (pyramids, two decoder
+    lanes), created once per device and shared by every StreamState.  HIP
+    spreads streams over a few hardware queues in creation order; streams
+    created anew for every driver would, after a few drivers, land on the
+    queue of another lane or of the caller's stream and serialise with it."""
+    d = torch.device(device)
+    key = d.index if d.index is not None else torch.cuda.current_device()
+    if key not in _PIPELINE_STREAMS:
+        _PIPELINE_STREAMS[key] = tuple(torch.cuda.Stream(device=d) for _ in range(3))
+    return _PIPELINE_STREAMS[key]
+
+
 class StreamState:
     """Streaming driver over the C ABI: O_1 = P_1; for each new frame, the
     pyramid of I_t (the previous frame's pyramid is kept), both flows decoded
@@ -411,8 +427,7 @@ class StreamState:
         self.bw = [torch.empty(n, 2, h, w, device=device) for _ in range(self.nd)]
         self.out = [torch.empty(n, 3, h, w, device=device), torch.empty(n, 3, h, w, device=device)]
         if pipelined:
-            self.s_pyr = torch.cuda.Stream(device=device)
-            self.s_dec = [torch.cuda.Stream(device=device) for _ in range(self.nd)]
+            self.s_pyr, *self.s_dec = _pipeline_streams(device)
         self.ev_pyr = [torch.cuda.Event() for _ in range(self.ns)]
         self.ev_dec = [torch.cuda.Event() for _ in range(self.ns)]   # by frame % ns
         self.ev_con = [torch.cuda.Event() for _ in range(self.nd)]   # by frame % nd
