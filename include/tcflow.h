@@ -211,10 +211,9 @@ TC_API void tc_paper_default_params(tc_paper_params* p);
  *                        (the setting of its results; = tc_paper_default_params)
  *   TC_PRESET_OBJECTIVE  k1 = k2 = 0.3, a_ph 10000, lambda 0.7, 150 iterations
  *                        (tuned for low warping error)
- *   TC_PRESET_FAST       the final setting with 50 iterations; the paper
- *                        pairs it with flow on half-sized inputs
- *                        (tc_flow_estimate_pair_half) and gives no iteration
- *                        count, 50 is this library's choice.
+ *   TC_PRESET_FAST       the final setting with 50 iterations (the runtime
+ *                        table's fast preset), paired with flow on
+ *                        half-sized inputs (tc_flow_estimate_pair_half).
  * Returns TC_ERR_INVALID_ARG for a null `p` or an unknown preset. */
 enum { TC_PRESET_FINAL = 0, TC_PRESET_OBJECTIVE = 1, TC_PRESET_FAST = 2 };
 TC_API int tc_paper_preset_params(int preset, tc_paper_params* p);

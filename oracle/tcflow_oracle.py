@@ -475,9 +475,9 @@ def warping_error(Vt, Vt1, flow_t_t1, mask):
 PAPER_DEFAULTS = dict(k1=0.3, k2=0.5, a_ph=6.5e3, lam=2.0, eta=0.15, kappa=0.2, iters=150)
 
 # Sec. 4.2, parameter settings: the final setting (= PAPER_DEFAULTS) and the
-# one tuned for low warping error ("objective"); Sec. 4.1: a fast preset with
-# fewer iterations (no count given; 50 is the reading taken here) used with
-# flow on half-sized inputs (flow_pair_half).
+# one tuned for low warping error ("objective"); Sec. 4.1 and the caption of
+# its runtime table: a fast preset with 50 iterations instead of 150, used
+# with flow on half-sized inputs (flow_pair_half).
 PAPER_PRESETS = {
     "final": dict(PAPER_DEFAULTS),
     "objective": dict(PAPER_DEFAULTS, k1=0.3, k2=0.3, a_ph=10e3, lam=0.7),
