@@ -312,9 +312,12 @@ __global__ __launch_bounds__(256) void conv_reduce_kernel(ConvArgs a) {
 // Two output channels on vector ALUs (FP32 activations).  A workgroup owns 8 x 32 output
 // pixels; its 4 waves split the input-channel chunks (wave w takes chunks
 // w, w + 4, ...) and each lane accumulates 4 pixels (rows r, r + 2, r + 4,
-// r + 6 of its column), so every weight read from LDS feeds 8 FMAs.  The
-// four per-wave partial sums are added in wave order at the end, so the
-// result does not depend on scheduling or on the batch.
+// r + 6 of its column), so every weight read from LDS feeds 8 FMAs.  Each
+// wave stages its chunk's halo in its own LDS tile (ordered by wave-level
+// fences, no workgroup barrier per chunk) and loads the next chunk's halo
+// into registers while it computes.  The four per-wave partial sums are
+// added in wave order at the end, so the result does not depend on
+// scheduling or on the batch.
 constexpr int HD_TY = 8, HD_TX = 32, HD_MAXCH = 16;
 
 template <typename T>
@@ -338,51 +341,71 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
   const int lx = lane & 31, ly0 = lane >> 5;  // lane's pixels: (ly0 + 2j, lx), j = 0..3
   float o0[4] = {0.f, 0.f, 0.f, 0.f}, o1[4] = {0.f, 0.f, 0.f, 0.f};
   const int rounds = (a.nchunks + 3) / 4;
+  // Each wave owns its LDS tile, so rounds need only wave-level ordering; the
+  // next chunk's halo is loaded into registers while this one is consumed.
+  constexpr int NR = (NPOS + 63) / 64;
+  f4 rlo[NR], rhi[NR];
+  auto fetch = [&](int ch) {
+    const View& v = ch < a.nb0 ? a.in0 : a.in1;
+    const int cb = (ch < a.nb0 ? ch : ch - a.nb0) + v.cb0;
+    const T* src = view_base_t<T>(v, img, in_plane * v.cbt) + (size_t)cb * in_plane;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int p = lane + 64 * k;
+      const int py = p / HX, px = p - py * HX;
+      const int gy = ty0 - 1 + py, gx = tx0 - 1 + px;
+      f4 lo = f4{0.f, 0.f, 0.f, 0.f}, hi = lo;
+      if (p < NPOS && gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w) {
+        float vv[8];
+        load8g(src + ((size_t)gy * a.in_w + gx) * 8, vv);
+        lo = f4{vv[0], vv[1], vv[2], vv[3]};
+        hi = f4{vv[4], vv[5], vv[6], vv[7]};
+      }
+      rlo[k] = lo;
+      rhi[k] = hi;
+    }
+  };
+  if (wave < a.nchunks) fetch(wave);
+  __syncthreads();  // s_w complete
   for (int r = 0; r < rounds; ++r) {
     const int ch = r * 4 + wave;
-    const bool active = ch < a.nchunks;
-    if (active) {
-      const View& v = ch < a.nb0 ? a.in0 : a.in1;
-      const int cb = (ch < a.nb0 ? ch : ch - a.nb0) + v.cb0;
-      const T* src = view_base_t<T>(v, img, in_plane * v.cbt) + (size_t)cb * in_plane;
-      for (int p = lane; p < NPOS; p += 64) {
-        const int py = p / HX, px = p - py * HX;
-        const int gy = ty0 - 1 + py, gx = tx0 - 1 + px;
-        f4 lo = f4{0.f, 0.f, 0.f, 0.f}, hi = lo;
-        if (gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w) {
-          float vv[8];
-          load8g(src + ((size_t)gy * a.in_w + gx) * 8, vv);
-          lo = f4{vv[0], vv[1], vv[2], vv[3]};
-          hi = f4{vv[4], vv[5], vv[6], vv[7]};
-        }
-        s_in[wave][0][p] = lo;
-        s_in[wave][1][p] = hi;
+    if (ch >= a.nchunks) break;  // wave-uniform; later rounds have no chunk either
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int p = lane + 64 * k;
+      if (p < NPOS) {
+        s_in[wave][0][p] = rlo[k];
+        s_in[wave][1][p] = rhi[k];
       }
     }
-    __syncthreads();
-    if (active) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (ch + 4 < a.nchunks) fetch(ch + 4);
 #pragma unroll
-      for (int tap = 0; tap < 9; ++tap) {
-        const int ty = tap / 3, tx = tap % 3;
-        const f4* wt = s_w + (ch * 9 + tap) * 4;
-        const f4 w01 = wt[0], w23 = wt[1], w45 = wt[2], w67 = wt[3];
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ty = tap / 3, tx = tap % 3;
+      const f4* wt = s_w + (ch * 9 + tap) * 4;
+      const f4 w01 = wt[0], w23 = wt[1], w45 = wt[2], w67 = wt[3];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int p = (ly0 + 2 * j + ty) * HX + lx + tx;
-          const f4 lo = s_in[wave][0][p], hi = s_in[wave][1][p];
-          o0[j] = fmaf(lo.x, w01.x, o0[j]); o1[j] = fmaf(lo.x, w01.y, o1[j]);
-          o0[j] = fmaf(lo.y, w01.z, o0[j]); o1[j] = fmaf(lo.y, w01.w, o1[j]);
-          o0[j] = fmaf(lo.z, w23.x, o0[j]); o1[j] = fmaf(lo.z, w23.y, o1[j]);
-          o0[j] = fmaf(lo.w, w23.z, o0[j]); o1[j] = fmaf(lo.w, w23.w, o1[j]);
-          o0[j] = fmaf(hi.x, w45.x, o0[j]); o1[j] = fmaf(hi.x, w45.y, o1[j]);
-          o0[j] = fmaf(hi.y, w45.z, o0[j]); o1[j] = fmaf(hi.y, w45.w, o1[j]);
-          o0[j] = fmaf(hi.z, w67.x, o0[j]); o1[j] = fmaf(hi.z, w67.y, o1[j]);
-          o0[j] = fmaf(hi.w, w67.z, o0[j]); o1[j] = fmaf(hi.w, w67.w, o1[j]);
-        }
+      for (int j = 0; j < 4; ++j) {
+        const int p = (ly0 + 2 * j + ty) * HX + lx + tx;
+        const f4 lo = s_in[wave][0][p], hi = s_in[wave][1][p];
+        o0[j] = fmaf(lo.x, w01.x, o0[j]); o1[j] = fmaf(lo.x, w01.y, o1[j]);
+        o0[j] = fmaf(lo.y, w01.z, o0[j]); o1[j] = fmaf(lo.y, w01.w, o1[j]);
+        o0[j] = fmaf(lo.z, w23.x, o0[j]); o1[j] = fmaf(lo.z, w23.y, o1[j]);
+        o0[j] = fmaf(lo.w, w23.z, o0[j]); o1[j] = fmaf(lo.w, w23.w, o1[j]);
+        o0[j] = fmaf(hi.x, w45.x, o0[j]); o1[j] = fmaf(hi.x, w45.y, o1[j]);
+        o0[j] = fmaf(hi.y, w45.z, o0[j]); o1[j] = fmaf(hi.y, w45.w, o1[j]);
+        o0[j] = fmaf(hi.z, w67.x, o0[j]); o1[j] = fmaf(hi.z, w67.y, o1[j]);
+        o0[j] = fmaf(hi.w, w67.z, o0[j]); o1[j] = fmaf(hi.w, w67.w, o1[j]);
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  __syncthreads();  // every wave done with s_in before it becomes s_red
   // per-wave partials -> LDS [wave][pixel][2], then one pixel per thread
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
