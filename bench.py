@@ -70,8 +70,8 @@ def c1_flops(desc, h, w, level=1, images=2):
 def wino_layer(h_l, w_l, cout):
     """Whether the library runs an FP32 stride-1 3x3 conv of this output
     size by Winograd F(2x2, 3x3): output channels a multiple of 32 and at
-    least 96 tiles of 16 x 16 pixels per image."""
-    return cout % 32 == 0 and (-(-h_l // 16)) * (-(-w_l // 16)) >= 96
+    least 32 tiles of 16 x 16 pixels per image."""
+    return cout % 32 == 0 and (-(-h_l // 16)) * (-(-w_l // 16)) >= 32
 
 
 def wino_flops(direct_flops, h_l, w_l):

@@ -416,10 +416,10 @@ int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, in
     const ConvPlan p = plan_conv(out_h, out_w, n, a.nchunks, stride, L.np);
     a.splits = p.splits;
     a.cps = p.cps;
-    // FP32 stride-1 layers with >= 96 tiles of 16 x 16 output pixels per
+    // FP32 stride-1 layers with >= 32 tiles of 16 x 16 output pixels per
     // image (a per-image rule, so the choice never depends on the batch):
     // Winograd F(2x2, 3x3) on the matrix cores, without split K
-    if (L.wu && (long)cdiv(out_h, 16) * cdiv(out_w, 16) >= 96 && wino_ok(a, stride, L.kc)) {
+    if (L.wu && (long)cdiv(out_h, 16) * cdiv(out_w, 16) >= 32 && wino_ok(a, stride, L.kc)) {
       a.splits = 1;
       a.cps = a.nchunks;
       e = launch_conv3x3_wino(a, L.wu, s);
