@@ -433,11 +433,13 @@ hipError_t launch_write_table(const PtrTable& t, int n, const void** dst, hipStr
 
 CvPlan plan_cost_volume(int h, int w, int C) {
   // Per-image geometry only (results do not depend on the batch): split the
-  // channel chunks when one image has fewer than 256 tiles.
+  // channel chunks when one image has fewer than 128 tiles (below that the
+  // grid leaves most CUs idle; above it the split's partial sums and their
+  // reduction pass cost more than they save).
   CvPlan p{1, C / 8};
   const long tiles = (long)cdiv(h, CV_TY) * cdiv(w, CV_TX);
   const int nch = C / 8;
-  if (tiles < 256 && nch > 1) {
+  if (tiles < 128 && nch > 1) {
     int splits = (int)((512 + tiles - 1) / tiles);
     if (splits > nch) splits = nch;
     p.cps = cdiv(nch, splits);
