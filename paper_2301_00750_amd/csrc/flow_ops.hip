@@ -174,10 +174,11 @@ __global__ __launch_bounds__(256) void flow_to_block_kernel(const float* __restr
 
 // ---------------------------------------------------------------- warp + cost volume
 //
-// A workgroup owns a TY x TX tile of pixels (one per thread).  Per chunk of 8
-// channels it gathers the warped second-image features on the tile plus a
-// halo of R pixels into LDS (bilinear, zero outside), then every thread
-// accumulates its (2R+1)^2 correlations from LDS.  Layout of the LDS tile:
+// A workgroup owns a TY x TX tile of pixels (one per thread).  The bilinear
+// taps of the tile plus a halo of R pixels (which taps lie inside the image,
+// and the fractional offsets) are computed once; then per chunk of 8 channels
+// it gathers the warped second-image features into LDS (zero outside), and
+// every thread accumulates its (2R+1)^2 correlations from LDS.  Layout of the LDS tile:
 // [2 float4 planes][halo positions][4] so that neighbouring lanes read
 // neighbouring 16-byte words.
 
@@ -195,6 +196,8 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
   constexpr int D = 2 * R + 1, NCV = D * D;
   constexpr int HY = CV_TY + 2 * R, HX = CV_TX + 2 * R, NPOS = HY * HX;
   __shared__ f4 s2[2][NPOS];
+  __shared__ int2 s_tap[NPOS];     // (pixel index of the top-left tap, validity bits of the 4 taps)
+  __shared__ float2 s_frac[NPOS];  // (ax, ay)
 
   const int tid = threadIdx.x;
   const int lx = tid % CV_TX, ly = tid / CV_TX;
@@ -214,33 +217,59 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
 #pragma unroll
   for (int k = 0; k < NCV; ++k) acc[k] = 0.f;
 
+  // The bilinear taps of every halo position (top-left pixel index, which of
+  // the 4 taps lie inside the image, fractional offsets) do not depend on the
+  // channel chunk: computed once, kept in LDS.
+  for (int p = tid; p < NPOS; p += 256) {
+    const int py = p / HX, px = p - py * HX;
+    const int Y = ty0 - R + py, X = tx0 - R + px;
+    int base = 0, mask = 0;
+    float ax = 0.f, ay = 0.f;
+    if (Y >= 0 && Y < h && X >= 0 && X < w) {
+      if (!U) {
+        base = Y * w + X;
+        mask = 1;
+      } else {
+        const float2v u = ldg(reinterpret_cast<const float2v*>(U + (size_t)Y * w + X));
+        const float fx = floorf(u.x), fy = floorf(u.y);
+        ax = u.x - fx;
+        ay = u.y - fy;
+        const int x0 = X + (int)fx, y0 = Y + (int)fy;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int xi = x0 + (t & 1), yi = y0 + (t >> 1);
+          if (xi >= 0 && xi < w && yi >= 0 && yi < h) mask |= 1 << t;
+        }
+        if (mask) base = y0 * w + x0;  // -1 <= x0 < w, -1 <= y0 < h here
+      }
+    }
+    s_tap[p] = int2{base, mask};
+    s_frac[p] = float2{ax, ay};
+  }
+  __syncthreads();
+
   for (int cb = cb_begin; cb < cb_end; ++cb) {
     const T* f2c = f2 + (size_t)cb * plane;
     for (int p = tid; p < NPOS; p += 256) {
-      const int py = p / HX, px = p - py * HX;
-      const int Y = ty0 - R + py, X = tx0 - R + px;
+      const int2 tp = s_tap[p];
       f4 lo = f4{0.f, 0.f, 0.f, 0.f}, hi = lo;
-      if (Y >= 0 && Y < h && X >= 0 && X < w) {
-        if (!U) {
+      if (!U) {
+        if (tp.y) {
           float v[8];
-          load8g(f2c + ((size_t)Y * w + X) * 8, v);
+          load8g(f2c + (size_t)tp.x * 8, v);
           lo = f4{v[0], v[1], v[2], v[3]};
           hi = f4{v[4], v[5], v[6], v[7]};
-        } else {
-          const float2v u = ldg(reinterpret_cast<const float2v*>(U + (size_t)Y * w + X));
-          const float fx = floorf(u.x), fy = floorf(u.y);
-          const float ax = u.x - fx, ay = u.y - fy;
-          const int x0 = X + (int)fx, y0 = Y + (int)fy;
+        }
+      } else {
+        const float2 fr = s_frac[p];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int xi = x0 + (t & 1), yi = y0 + (t >> 1);
-            const float wt = ((t & 1) ? ax : 1.f - ax) * ((t >> 1) ? ay : 1.f - ay);
-            if (xi >= 0 && xi < w && yi >= 0 && yi < h) {
-              float v[8];
-              load8g(f2c + ((size_t)yi * w + xi) * 8, v);
-              lo += wt * f4{v[0], v[1], v[2], v[3]};
-              hi += wt * f4{v[4], v[5], v[6], v[7]};
-            }
+        for (int t = 0; t < 4; ++t) {
+          if ((tp.y >> t) & 1) {
+            const float wt = ((t & 1) ? fr.x : 1.f - fr.x) * ((t >> 1) ? fr.y : 1.f - fr.y);
+            float v[8];
+            load8g(f2c + ((size_t)tp.x + (t & 1) + (t >> 1) * (size_t)w) * 8, v);
+            lo += wt * f4{v[0], v[1], v[2], v[3]};
+            hi += wt * f4{v[4], v[5], v[6], v[7]};
           }
         }
       }
