@@ -311,6 +311,24 @@ def test_fp32_winograd_levels_ragged_vs_oracle(tc):
         assert mean <= 0.05 and mx <= 0.05
 
 
+def test_fp32_winograd_batch_invariance_and_determinism(tc):
+    """At sizes where levels 1-4 run by Winograd (and level 3's cost volume
+    without channel splits), a batch of two pairs gives each pair exactly
+    what it gives alone, and a repeated call gives the same bits."""
+    d = synth.load_desc("tiny")
+    net = tc.Net(d, synth.he_weights(d))
+    gen = torch.Generator().manual_seed(8)
+    A = torch.rand(2, 3, 1040, 1680, generator=gen)
+    B = torch.rand(2, 3, 1040, 1680, generator=gen)
+    say("[flow] Winograd sizes: batch of 2 vs alone, repeat")
+    fw, bw = net.flow_estimate_pair(g(A), g(B))
+    fw2, bw2 = net.flow_estimate_pair(g(A), g(B))
+    s1 = net.flow_estimate_pair(g(A[1:]), g(B[1:]))
+    torch.cuda.synchronize()
+    assert torch.equal(fw, fw2) and torch.equal(bw, bw2)
+    assert torch.equal(s1[0][0], fw[1]) and torch.equal(s1[1][0], bw[1])
+
+
 # ---------------------------------------------------------------- BF16 precision form
 #
 # Convolutions and the cost volume read BF16 activations and weights and
