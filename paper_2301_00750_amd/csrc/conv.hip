@@ -714,7 +714,7 @@ ConvPlan plan_conv(int out_h, int out_w, int n, int nchunks, int stride, int np)
     return p;
   }
   const long t8 = (long)cdiv(out_h, 8) * cdiv(out_w, TW);
-  if (t8 < kTarget / 2) {
+  if (t8 < kTarget / 4) {
     int splits = (int)((kTarget + t8 - 1) / t8);
     if (splits > 16) splits = 16;
     if (splits > nchunks) splits = nchunks;
