@@ -701,9 +701,10 @@ int grid_1d(size_t total) {
 }  // namespace
 
 ConvPlan plan_conv(int out_h, int out_w, int n, int nchunks, int stride, int np) {
-  // Aim for >= ~512 workgroups per image (256 CUs, images usually come in
-  // pairs).  Large layers take the 16-row tile; small ones the 8-row tile and
-  // split K to make up the rest.  The plan depends on the per-image geometry
+  // Large layers take the 16-row tile; small ones the 8-row tile, and below
+  // 128 tiles per image split K towards ~512 workgroups (at 128-255 tiles the
+  // two images of a decoder batch already fill the 256 CUs, and the split's
+  // partial sums and reduction pass cost more than they gain).  The plan depends on the per-image geometry
   // only, never on the batch size n, so the summation order of every output
   // (and hence its value, bit for bit) is the same alone and in a batch.
   (void)n;
