@@ -90,12 +90,13 @@ __global__ __launch_bounds__(256) void consistency_kernel(
     const float* P, const float* __restrict__ Oprev, const float* __restrict__ ffw,
     const float* __restrict__ fbw, float alpha, int n, int h, int w, float* out,
     unsigned char* __restrict__ mask) {
+  // grid: x over 256-pixel pieces of a row, y = row, z = image (no index
+  // division per pixel)
   const size_t plane = (size_t)h * w;
-  const size_t total = (size_t)n * plane;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const size_t img = i / plane, pix = i - img * plane;
-    const int y = (int)(pix / w), x = (int)(pix - (size_t)y * w);
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y;
+  const size_t img = blockIdx.z;
+  if (x < w) {
+    const size_t pix = (size_t)y * w + x, i = img * plane + pix;
     const Vis v = visibility(ffw + img * 2 * plane, fbw + img * 2 * plane, plane, pix, x, y, w, h);
     const bool vis = v.vis;
     const float w00 = v.w00, w01 = v.w01, w10 = v.w10, w11 = v.w11;
@@ -141,9 +142,8 @@ hipError_t launch_consistency(const float* P, const float* Oprev, const float* f
                               unsigned char* mask, hipStream_t s) {
   const size_t total = (size_t)n * h * w;
   if (!total) return hipSuccess;
-  size_t g = (total + 255) / 256;
-  if (g > 1 << 20) g = 1 << 20;
-  consistency_kernel<<<(unsigned)g, 256, 0, s>>>(P, Oprev, ffw, fbw, alpha, n, h, w, out, mask);
+  consistency_kernel<<<dim3(cdiv(w, 256), h, n), 256, 0, s>>>(P, Oprev, ffw, fbw, alpha, n, h, w,
+                                                              out, mask);
   return hipGetLastError();
 }
 

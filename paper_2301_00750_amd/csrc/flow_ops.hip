@@ -13,14 +13,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void stage_kernel(const float* __restrict__ frames, int n, int h,
                                                     int w, T* __restrict__ out, int hp, int wp,
                                                     unsigned* aout) {
-  // grid: x over the pixels of one image, y = image
-  const int img = blockIdx.y;
+  // grid: x over 256-pixel pieces of a row, y = row, z = image (no index
+  // division per pixel)
+  const int img = blockIdx.z, y = blockIdx.y;
+  const int x = blockIdx.x * 256 + threadIdx.x;
   const size_t per = (size_t)hp * wp;
   float mx = 0.f;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const int x = (int)(i % wp);
-    const int y = (int)(i / wp);
+  if (x < wp) {
+    const size_t i = (size_t)y * wp + x;
     const int sy = y < h ? y : h - 1, sx = x < w ? x : w - 1;
     const size_t plane = (size_t)h * w;
     const float* f = frames + (size_t)img * 3 * plane + (size_t)sy * w + sx;
@@ -91,13 +91,10 @@ __global__ __launch_bounds__(256) void final_flow_kernel(const float* __restrict
                                                          float* __restrict__ out_a,
                                                          float* __restrict__ out_b, int nsplit,
                                                          int H, int W, float* const* out_tab) {
-  const size_t total = (size_t)n * H * W;
+  // grid: x over 256-pixel pieces of a row, y = row, z = image
   const float sc = (float)scale, inv_s = 1.f / (float)scale;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const int x = (int)(i % W);
-    const int y = (int)((i / W) % H);
-    const int img = (int)(i / ((size_t)W * H));
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, img = blockIdx.z;
+  if (x < W) {
     int y0, y1, x0, x1;
     float fy, fx;
     up_taps(y, hf, inv_s, y0, y1, fy);
@@ -388,7 +385,7 @@ hipError_t launch_stage(const float* frames, int n, int h, int w, float* out, in
                         int bf16act, unsigned* aout, hipStream_t s) {
   const size_t per = (size_t)hp * wp;
   if (!per || n <= 0) return hipSuccess;
-  dim3 grid(grid_for(per), n);
+  dim3 grid(cdiv(wp, 256), hp, n);
   if (bf16act)
     stage_kernel<bf16><<<grid, 256, 0, s>>>(frames, n, h, w, reinterpret_cast<bf16*>(out), hp, wp,
                                             aout);
@@ -417,7 +414,7 @@ hipError_t launch_final_flow(const float* flow_f, int n, int hf, int wf, int sca
   if (!total) return hipSuccess;
   if (scale < 2 || (scale & (scale - 1)) || (long)hf * scale < H || (long)wf * scale < W)
     return hipErrorInvalidValue;
-  final_flow_kernel<<<grid_for(total), 256, 0, s>>>(flow_f, n, hf, wf, scale, out_a, out_b, nsplit,
+  final_flow_kernel<<<dim3(cdiv(W, 256), H, n), 256, 0, s>>>(flow_f, n, hf, wf, scale, out_a, out_b, nsplit,
                                                     H, W, out_tab);
   return hipGetLastError();
 }
