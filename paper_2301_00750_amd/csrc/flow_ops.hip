@@ -189,7 +189,7 @@ __device__ inline const T* vbase(const View& v, int img, size_t img_elems) {
 }
 
 template <int R, typename T>
-__global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void warp_cv_kernel(CvArgs a) {
   constexpr int D = 2 * R + 1, NCV = D * D;
   constexpr int HY = CV_TY + 2 * R, HX = CV_TX + 2 * R, NPOS = HY * HX;
   __shared__ f4 s2[2][NPOS];
@@ -245,19 +245,27 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
   }
   __syncthreads();
 
+  // With FP32 activations the tap loads are unconditional: an index clamped
+  // into the image plane, the value of a tap outside the image replaced by
+  // zero after the load, so the 4 taps' loads are in flight together (loads
+  // inside per-tap branches each wait for their data at the branch join).
+  // With BF16 activations the branches measured faster.
+  const int last_px = h * w - 1;
   for (int cb = cb_begin; cb < cb_end; ++cb) {
     const T* f2c = f2 + (size_t)cb * plane;
     for (int p = tid; p < NPOS; p += 256) {
       const int2 tp = s_tap[p];
       f4 lo = f4{0.f, 0.f, 0.f, 0.f}, hi = lo;
       if (!U) {
-        if (tp.y) {
+        if (sizeof(T) == 4 || tp.y) {
           float v[8];
-          load8g(f2c + (size_t)tp.x * 8, v);
-          lo = f4{v[0], v[1], v[2], v[3]};
-          hi = f4{v[4], v[5], v[6], v[7]};
+          load8g(f2c + (size_t)tp.x * 8, v);  // tp.x = 0 when the position is outside
+          if (tp.y) {
+            lo = f4{v[0], v[1], v[2], v[3]};
+            hi = f4{v[4], v[5], v[6], v[7]};
+          }
         }
-      } else {
+      } else if constexpr (sizeof(T) == 2) {
         const float2 fr = s_frac[p];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -268,6 +276,21 @@ __global__ __launch_bounds__(256) void warp_cv_kernel(CvArgs a) {
             lo += wt * f4{v[0], v[1], v[2], v[3]};
             hi += wt * f4{v[4], v[5], v[6], v[7]};
           }
+        }
+      } else {
+        const float2 fr = s_frac[p];
+        float v[4][8];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          load8g(f2c + (size_t)min(max(tp.x + (t & 1) + (t >> 1) * w, 0), last_px) * 8, v[t]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const bool in = (tp.y >> t) & 1;
+          const float wt = ((t & 1) ? fr.x : 1.f - fr.x) * ((t >> 1) ? fr.y : 1.f - fr.y);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[t][e] = in ? v[t][e] : 0.f;
+          lo += wt * f4{v[t][0], v[t][1], v[t][2], v[t][3]};
+          hi += wt * f4{v[t][4], v[t][5], v[t][6], v[t][7]};
         }
       }
       s2[0][p] = lo;
