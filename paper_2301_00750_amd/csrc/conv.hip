@@ -311,13 +311,16 @@ __global__ __launch_bounds__(256) void conv_reduce_kernel(ConvArgs a) {
 //
 // Two output channels on vector ALUs (FP32 activations).  A workgroup owns 8 x 32 output
 // pixels; its 4 waves split the input-channel chunks (wave w takes chunks
-// w, w + 4, ...) and each lane accumulates 4 pixels (rows r, r + 2, r + 4,
-// r + 6 of its column), so every weight read from LDS feeds 8 FMAs.  Each
-// wave stages its chunk's halo in its own LDS tile (ordered by wave-level
-// fences, no workgroup barrier per chunk) and loads the next chunk's halo
-// into registers while it computes.  The four per-wave partial sums are
-// added in wave order at the end, so the result does not depend on
-// scheduling or on the batch.
+// w, w + 4, ...) and each lane accumulates 4 consecutive pixels of its
+// column (rows 4g .. 4g + 3, g = lane / 32): each of the 6 input rows under
+// them is read from LDS once per column tap and feeds up to 3 of the 4
+// pixels.  The weights are staged in LDS once per workgroup; a wave reads a
+// column tap's three row taps into registers (broadcast reads) before the
+// six input rows under them.  Each wave stages its chunk's
+// halo in its own LDS tile (ordered by wave-level fences, no workgroup
+// barrier per chunk) and loads the next chunk's halo into registers while it
+// computes.  The four per-wave partial sums are added in wave order at the
+// end, so the result does not depend on scheduling or on the batch.
 constexpr int HD_TY = 8, HD_TX = 32, HD_MAXCH = 16;
 
 template <typename T>
@@ -338,7 +341,7 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
     s_w[i] = f4{src[0], src[1], src[a.np], src[a.np + 1]};
   }
 
-  const int lx = lane & 31, ly0 = lane >> 5;  // lane's pixels: (ly0 + 2j, lx), j = 0..3
+  const int lx = lane & 31, ly0 = 4 * (lane >> 5);  // lane's pixels: (ly0 + j, lx), j = 0..3
   float o0[4] = {0.f, 0.f, 0.f, 0.f}, o1[4] = {0.f, 0.f, 0.f, 0.f};
   const int rounds = (a.nchunks + 3) / 4;
   // Each wave owns its LDS tile, so rounds need only wave-level ordering; the
@@ -383,22 +386,29 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (ch + 4 < a.nchunks) fetch(ch + 4);
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-      const int ty = tap / 3, tx = tap % 3;
-      const f4* wt = s_w + (ch * 9 + tap) * 4;
-      const f4 w01 = wt[0], w23 = wt[1], w45 = wt[2], w67 = wt[3];
+    for (int tx = 0; tx < 3; ++tx) {
+      f4 wr[3][4];  // row taps ty = 0..2 of column tap tx: (w0, w1) of channels 2k, 2k + 1
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int p = (ly0 + 2 * j + ty) * HX + lx + tx;
+      for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) wr[ty][k] = s_w[(ch * 9 + ty * 3 + tx) * 4 + k];
+#pragma unroll
+      for (int rr = 0; rr < 6; ++rr) {  // input row ly0 + rr feeds pixel j = rr - ty
+        const int p = (ly0 + rr) * HX + lx + tx;
         const f4 lo = s_in[wave][0][p], hi = s_in[wave][1][p];
-        o0[j] = fmaf(lo.x, w01.x, o0[j]); o1[j] = fmaf(lo.x, w01.y, o1[j]);
-        o0[j] = fmaf(lo.y, w01.z, o0[j]); o1[j] = fmaf(lo.y, w01.w, o1[j]);
-        o0[j] = fmaf(lo.z, w23.x, o0[j]); o1[j] = fmaf(lo.z, w23.y, o1[j]);
-        o0[j] = fmaf(lo.w, w23.z, o0[j]); o1[j] = fmaf(lo.w, w23.w, o1[j]);
-        o0[j] = fmaf(hi.x, w45.x, o0[j]); o1[j] = fmaf(hi.x, w45.y, o1[j]);
-        o0[j] = fmaf(hi.y, w45.z, o0[j]); o1[j] = fmaf(hi.y, w45.w, o1[j]);
-        o0[j] = fmaf(hi.z, w67.x, o0[j]); o1[j] = fmaf(hi.z, w67.y, o1[j]);
-        o0[j] = fmaf(hi.w, w67.z, o0[j]); o1[j] = fmaf(hi.w, w67.w, o1[j]);
+        const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+        for (int ty = 0; ty < 3; ++ty) {
+          const int j = rr - ty;
+          if (j < 0 || j > 3) continue;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            o0[j] = fmaf(v[2 * k], wr[ty][k].x, o0[j]);
+            o1[j] = fmaf(v[2 * k], wr[ty][k].y, o1[j]);
+            o0[j] = fmaf(v[2 * k + 1], wr[ty][k].z, o0[j]);
+            o1[j] = fmaf(v[2 * k + 1], wr[ty][k].w, o1[j]);
+          }
+        }
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -409,7 +419,7 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
   // per-wave partials -> LDS [wave][pixel][2], then one pixel per thread
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int pix = (ly0 + 2 * j) * HD_TX + lx;
+    const int pix = (ly0 + j) * HD_TX + lx;
     s_red[(wave * 256 + pix) * 2 + 0] = o0[j];
     s_red[(wave * 256 + pix) * 2 + 1] = o1[j];
   }
@@ -766,7 +776,7 @@ hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, int mr, hipStre
 
 hipError_t launch_head(const ConvArgs& a, hipStream_t s) {
   if (a.n <= 0 || a.out_h <= 0 || a.out_w <= 0) return hipSuccess;
-  if (a.cout != 2 || a.np != 16 || a.nchunks > HD_MAXCH) return hipErrorInvalidValue;
+  if (a.cout != 2 || a.np != 16 || a.nchunks < 1 || a.nchunks > HD_MAXCH) return hipErrorInvalidValue;
   dim3 grid(cdiv(a.out_w, HD_TX), cdiv(a.out_h, HD_TY), a.n);
   if (a.bf16act)
     head_kernel<bf16><<<grid, 256, 0, s>>>(a);
