@@ -253,6 +253,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void w
   const int last_px = h * w - 1;
   for (int cb = cb_begin; cb < cb_end; ++cb) {
     const T* f2c = f2 + (size_t)cb * plane;
+    // BF16: this pixel's F1 chunk (one 16-byte word) is loaded before the
+    // gather so that its latency overlaps the gather and the barrier (with
+    // FP32 activations the 8 registers this takes spill)
+    u4 f1w = u4{0, 0, 0, 0};
+    if constexpr (sizeof(T) == 2)
+      f1w = ldg(reinterpret_cast<const u4*>(f1 + (size_t)cb * plane +
+                                            ((size_t)(valid ? y : 0) * w + (valid ? x : 0)) * 8));
     for (int p = tid; p < NPOS; p += 256) {
       const int2 tp = s_tap[p];
       f4 lo = f4{0.f, 0.f, 0.f, 0.f}, hi = lo;
@@ -299,7 +306,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void w
     __syncthreads();
     if (valid) {
       float v1[8];
-      load8g(f1 + (size_t)cb * plane + ((size_t)y * w + x) * 8, v1);
+      if constexpr (sizeof(T) == 2) {
+        const unsigned wd[4] = {f1w.x, f1w.y, f1w.z, f1w.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          v1[2 * k] = __uint_as_float(wd[k] << 16);
+          v1[2 * k + 1] = __uint_as_float(wd[k] & 0xffff0000u);
+        }
+      } else {
+        load8g(f1 + (size_t)cb * plane + ((size_t)y * w + x) * 8, v1);
+      }
       const f4 a0 = f4{v1[0], v1[1], v1[2], v1[3]}, a1 = f4{v1[4], v1[5], v1[6], v1[7]};
 #pragma unroll
       for (int dy = 0; dy < D; ++dy)
