@@ -309,18 +309,18 @@ __global__ __launch_bounds__(256) void conv_reduce_kernel(ConvArgs a) {
 
 // ---------------------------------------------------------------- head
 //
-// Two output channels on vector ALUs (FP32 activations).  A workgroup owns 8 x 32 output
-// pixels; its 4 waves split the input-channel chunks (wave w takes chunks
-// w, w + 4, ...) and each lane accumulates 4 consecutive pixels of its
-// column (rows 4g .. 4g + 3, g = lane / 32): each of the 6 input rows under
-// them is read from LDS once per column tap and feeds up to 3 of the 4
+// Two output channels on vector ALUs (FP32 activations).  A workgroup owns
+// 8 x 32 output pixels; its 4 waves split the input-channel chunks (wave w
+// takes chunks w, w + 4, ...) and each lane accumulates 4 consecutive pixels
+// of its column (rows 4g .. 4g + 3, g = lane / 32): each of the 6 input rows
+// under them is read from LDS once per column tap and feeds up to 3 of the 4
 // pixels.  The weights are staged in LDS once per workgroup; a wave reads a
 // column tap's three row taps into registers (broadcast reads) before the
-// six input rows under them.  Each wave stages its chunk's
-// halo in its own LDS tile (ordered by wave-level fences, no workgroup
-// barrier per chunk) and loads the next chunk's halo into registers while it
-// computes.  The four per-wave partial sums are added in wave order at the
-// end, so the result does not depend on scheduling or on the batch.
+// six input rows under them.  Each wave stages its chunk's halo in its own
+// LDS tile (ordered by wave-level fences, no workgroup barrier per chunk) and
+// loads the next chunk's halo into registers while it computes.  The four
+// per-wave partial sums are added in wave order at the end, so the result
+// does not depend on scheduling or on the batch.
 constexpr int HD_TY = 8, HD_TX = 32, HD_MAXCH = 16;
 
 template <typename T>
