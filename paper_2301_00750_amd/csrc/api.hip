@@ -406,8 +406,10 @@ int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, in
   a.partial = partial;
   hipError_t e;
   probe_begin(stage, s);
-  if (!act_bf16 && L.cout == 2 && compact && stride == 1 && L.kc == 8) {
-    // FP32 estimator head on vector ALUs
+  if (L.cout == 2 && compact && stride == 1 && L.kc == 8 && !L.bf16 && !L.fp8) {
+    // estimator head on vector ALUs (FP32 weights; BF16 activations are
+    // multiplied as bfloat16 pairs)
+    a.bf16act = act_bf16 ? 1 : 0;
     a.splits = 1;
     a.nchunks = L.cin_pad / 8;
     a.cps = a.nchunks;
@@ -692,7 +694,7 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     Packed pk;
     int np = 0;
     cl.fp8 = net->fp8 && !head && fp8_ok;
-    cl.bf16 = net->bf16act && !cl.fp8;
+    cl.bf16 = net->bf16act && !cl.fp8 && !head;  // heads: FP32 packing for the vector-ALU head
     cl.ws = nullptr;
     if (cl.fp8) {
       std::vector<uint8_t> wq;

@@ -326,19 +326,35 @@ constexpr int HD_TY = 8, HD_TX = 32, HD_MAXCH = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
   constexpr int HY = HD_TY + 2, HX = HD_TX + 2, NPOS = HY * HX;
-  __shared__ f4 s_in[4][2][NPOS];               // per wave: one 8-channel halo tile
-  __shared__ f4 s_w[HD_MAXCH * 9 * 4];          // [chunk][tap][channel pair] (w0 w1 of 2 channels)
-  float* s_red = reinterpret_cast<float*>(&s_in[0][0][0]);
+  // FP32 activations: per wave one 8-channel halo tile as two float4 planes,
+  // weights [chunk][tap][channel pair] = (w0(c), w1(c), w0(c+1), w1(c+1)).
+  // BF16 activations: the tile as one plane of 8 bfloat16 per position,
+  // weights [chunk][tap][output] = 4 bfloat16 pairs (channels 2k, 2k + 1),
+  // multiplied with v_dot2_f32_bf16 into FP32 sums.
+  constexpr bool BF = sizeof(T) == 2;
+  constexpr int PLANES = BF ? 1 : 2;
+  __shared__ u4 s_in[4 * PLANES * NPOS];
+  __shared__ u4 s_w[HD_MAXCH * 9 * (BF ? 2 : 4)];
+  float* s_red = reinterpret_cast<float*>(&s_in[0]);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tx0 = blockIdx.x * HD_TX, ty0 = blockIdx.y * HD_TY, img = blockIdx.z;
   const size_t in_plane = (size_t)a.in_h * a.in_w * 8;
 
   // weights: packed [chunk][tap][8][np] -> s_w[(chunk * 9 + tap) * 4 + pair] = (w0(c), w1(c), w0(c+1), w1(c+1))
-  for (int i = tid; i < a.nchunks * 9 * 4; i += 256) {
-    const int pair = i & 3, ct = i >> 2;
-    const float* src = a.w + (size_t)ct * 8 * a.np + 2 * pair * a.np;
-    s_w[i] = f4{src[0], src[1], src[a.np], src[a.np + 1]};
+  if constexpr (BF) {
+    for (int i = tid; i < a.nchunks * 9 * 2; i += 256) {
+      const int o = i & 1, ct = i >> 1;
+      const float* src = a.w + (size_t)ct * 8 * a.np + o;
+      s_w[i] = u4{pack2(src[0], src[a.np]), pack2(src[2 * a.np], src[3 * a.np]),
+                  pack2(src[4 * a.np], src[5 * a.np]), pack2(src[6 * a.np], src[7 * a.np])};
+    }
+  } else {
+    for (int i = tid; i < a.nchunks * 9 * 4; i += 256) {
+      const int pair = i & 3, ct = i >> 2;
+      const float* src = a.w + (size_t)ct * 8 * a.np + 2 * pair * a.np;
+      s_w[i] = __builtin_bit_cast(u4, f4{src[0], src[1], src[a.np], src[a.np + 1]});
+    }
   }
 
   const int lx = lane & 31, ly0 = 4 * (lane >> 5);  // lane's pixels: (ly0 + j, lx), j = 0..3
@@ -347,7 +363,7 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
   // Each wave owns its LDS tile, so rounds need only wave-level ordering; the
   // next chunk's halo is loaded into registers while this one is consumed.
   constexpr int NR = (NPOS + 63) / 64;
-  f4 rlo[NR], rhi[NR];
+  u4 rlo[NR], rhi[NR];  // BF16: the raw 16-byte word in rlo
   auto fetch = [&](int ch) {
     const View& v = ch < a.nb0 ? a.in0 : a.in1;
     const int cb = (ch < a.nb0 ? ch : ch - a.nb0) + v.cb0;
@@ -357,12 +373,15 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
       const int p = lane + 64 * k;
       const int py = p / HX, px = p - py * HX;
       const int gy = ty0 - 1 + py, gx = tx0 - 1 + px;
-      f4 lo = f4{0.f, 0.f, 0.f, 0.f}, hi = lo;
+      u4 lo = u4{0, 0, 0, 0}, hi = lo;
       if (p < NPOS && gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w) {
-        float vv[8];
-        load8g(src + ((size_t)gy * a.in_w + gx) * 8, vv);
-        lo = f4{vv[0], vv[1], vv[2], vv[3]};
-        hi = f4{vv[4], vv[5], vv[6], vv[7]};
+        if constexpr (BF) {
+          lo = ldg(reinterpret_cast<const u4*>(src + ((size_t)gy * a.in_w + gx) * 8));
+        } else {
+          const f4* q = reinterpret_cast<const f4*>(src + ((size_t)gy * a.in_w + gx) * 8);
+          lo = __builtin_bit_cast(u4, ldg(q));
+          hi = __builtin_bit_cast(u4, ldg(q + 1));
+        }
       }
       rlo[k] = lo;
       rhi[k] = hi;
@@ -377,25 +396,55 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
     for (int k = 0; k < NR; ++k) {
       const int p = lane + 64 * k;
       if (p < NPOS) {
-        s_in[wave][0][p] = rlo[k];
-        s_in[wave][1][p] = rhi[k];
+        s_in[(wave * PLANES) * NPOS + p] = rlo[k];
+        if constexpr (!BF) s_in[(wave * PLANES + 1) * NPOS + p] = rhi[k];
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (ch + 4 < a.nchunks) fetch(ch + 4);
+    if constexpr (BF) {
+#pragma unroll
+      for (int tx = 0; tx < 3; ++tx) {
+        unsigned wr[3][2][4];  // row taps ty = 0..2 of column tap tx, outputs 0 and 1
+#pragma unroll
+        for (int ty = 0; ty < 3; ++ty)
+#pragma unroll
+          for (int o = 0; o < 2; ++o) {
+            const u4 q = s_w[(ch * 9 + ty * 3 + tx) * 2 + o];
+            wr[ty][o][0] = q.x; wr[ty][o][1] = q.y; wr[ty][o][2] = q.z; wr[ty][o][3] = q.w;
+          }
+#pragma unroll
+        for (int rr = 0; rr < 6; ++rr) {  // input row ly0 + rr feeds pixel j = rr - ty
+          const u4 q = s_in[(wave * PLANES) * NPOS + (ly0 + rr) * HX + lx + tx];
+          const unsigned v[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+          for (int ty = 0; ty < 3; ++ty) {
+            const int j = rr - ty;
+            if (j < 0 || j > 3) continue;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const bf16x2 x = __builtin_bit_cast(bf16x2, v[k]);
+              o0[j] = __builtin_amdgcn_fdot2_f32_bf16(x, __builtin_bit_cast(bf16x2, wr[ty][0][k]), o0[j], false);
+              o1[j] = __builtin_amdgcn_fdot2_f32_bf16(x, __builtin_bit_cast(bf16x2, wr[ty][1][k]), o1[j], false);
+            }
+          }
+        }
+      }
+    } else
 #pragma unroll
     for (int tx = 0; tx < 3; ++tx) {
       f4 wr[3][4];  // row taps ty = 0..2 of column tap tx: (w0, w1) of channels 2k, 2k + 1
 #pragma unroll
       for (int ty = 0; ty < 3; ++ty)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) wr[ty][k] = s_w[(ch * 9 + ty * 3 + tx) * 4 + k];
+        for (int k = 0; k < 4; ++k) wr[ty][k] = __builtin_bit_cast(f4, s_w[(ch * 9 + ty * 3 + tx) * 4 + k]);
 #pragma unroll
       for (int rr = 0; rr < 6; ++rr) {  // input row ly0 + rr feeds pixel j = rr - ty
         const int p = (ly0 + rr) * HX + lx + tx;
-        const f4 lo = s_in[wave][0][p], hi = s_in[wave][1][p];
+        const f4 lo = __builtin_bit_cast(f4, s_in[(wave * PLANES) * NPOS + p]);
+        const f4 hi = __builtin_bit_cast(f4, s_in[(wave * PLANES + 1) * NPOS + p]);
         const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
         for (int ty = 0; ty < 3; ++ty) {
