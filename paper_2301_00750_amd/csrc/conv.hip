@@ -309,8 +309,9 @@ __global__ __launch_bounds__(256) void conv_reduce_kernel(ConvArgs a) {
 
 // ---------------------------------------------------------------- head
 //
-// Two output channels on vector ALUs (FP32 activations).  A workgroup owns
-// 8 x 32 output pixels; its 4 waves split the input-channel chunks (wave w
+// Two output channels on vector ALUs (FP32 weights in the packed order of
+// the FP32 conv; FP32 or BF16 activations).  A workgroup owns 8 x 32 output
+// pixels; its 4 waves split the input-channel chunks (wave w
 // takes chunks w, w + 4, ...) and each lane accumulates 4 consecutive pixels
 // of its column (rows 4g .. 4g + 3, g = lane / 32): each of the 6 input rows
 // under them is read from LDS once per column tap and feeds up to 3 of the 4
