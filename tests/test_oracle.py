@@ -379,6 +379,67 @@ def test_sequence_first_frame_and_epe():
     assert np.isclose(O.epe(a, b), 5.0)
 
 
+def test_sequence_zero_flow_net_is_running_blend():
+    """A network with all-zero weights gives zero flow in both directions, so
+    every pixel is visible, G = O_{t-1} and the recursion is
+    O_t = (1 - a) P_t + a O_{t-1}: O_3 = (1 - a) P_3 + a (1 - a) P_2 + a^2 P_1.
+    Feeding P_{t-1} instead of O_{t-1}, or dropping a term, changes O_3."""
+    d = synth.load_desc("tiny")
+    wts = _zero_weights(d)
+    h, w = 20, 28
+    I = [RNG.random((3, h, w)) for _ in range(4)]
+    P = [RNG.random((3, h, w)) for _ in range(4)]
+    a = 0.375  # exact in binary
+    outs = O.run_sequence(I, P, wts, d, a)
+    assert len(outs) == 4 and np.array_equal(outs[0], P[0])
+    exp = [P[0]]
+    for t in range(1, 4):
+        exp.append((1 - a) * P[t] + a * exp[-1])
+    for t in range(4):
+        assert np.allclose(outs[t], exp[t], rtol=0, atol=1e-15)
+    closed = (1 - a) * P[2] + a * (1 - a) * P[1] + a * a * P[0]
+    assert np.allclose(outs[2], closed, rtol=0, atol=1e-15)
+
+
+def test_sequence_shift_flows_feed_back_output(monkeypatch):
+    """The recursion with the flow pair replaced by a stub that recognises an
+    integer shift between its two arguments and returns its exact flows:
+    frames move by (dx, dy) = (2, -1) each step, so flow(I_{t-1} -> I_t) is
+    (2, -1) and flow(I_t -> I_{t-1}) is (-2, 1).  Then
+    O_t(y, x) = (1 - a) P_t(y, x) + a O_{t-1}(y + 1, x - 2) where that pixel
+    exists, and P_t(y, x) elsewhere (occluded: the source leaves the frame).
+    This fixes the argument order of the flow pair, which flow warps
+    O_{t-1}, and that O_{t-1} (not P_{t-1}) is fed back."""
+    h, w, dx, dy = 18, 25, 2, -1
+    base = RNG.random((3, h + 16, w + 16))
+    I = [base[:, 8 - t * dy:8 - t * dy + h, 8 - t * dx:8 - t * dx + w] for t in range(4)]
+    # I_t(y, x) = I_{t-1}(y - dy, x - dx): content moves by (dx, dy)
+    for t in range(1, 4):
+        assert np.array_equal(I[t][:, :-1, 2:], I[t - 1][:, 1:, :-2])
+
+    def stub_pair(A, B, wts, desc):
+        for sx in range(-3, 4):
+            for sy in range(-3, 4):
+                ys, xs = slice(max(sy, 0), h + min(sy, 0)), slice(max(sx, 0), w + min(sx, 0))
+                yd, xd = slice(max(-sy, 0), h + min(-sy, 0)), slice(max(-sx, 0), w + min(-sx, 0))
+                if np.array_equal(B[:, ys, xs], A[:, yd, xd]):
+                    one = np.ones((h, w))
+                    return np.stack([sx * one, sy * one]), np.stack([-sx * one, -sy * one])
+        raise AssertionError("frames are not an integer shift of each other")
+
+    monkeypatch.setattr(O, "flow_pair", stub_pair)
+    P = [RNG.random((3, h, w)) for _ in range(4)]
+    a = 0.75
+    outs = O.run_sequence(I, P, None, None, a)
+    exp = [P[0]]
+    for t in range(1, 4):
+        o = P[t].copy()
+        o[:, :h - 1, dx:] = (1 - a) * P[t][:, :h - 1, dx:] + a * exp[-1][:, 1:, :w - dx]
+        exp.append(o)
+    for t in range(4):
+        assert np.allclose(outs[t], exp[t], rtol=0, atol=1e-15), t
+
+
 def test_warping_error_nonincreasing_in_alpha():
     """Exact flows of an integer shift: E_warp(O_1, O_2) over the visible set
     scales with (1 - alpha)."""
