@@ -46,7 +46,8 @@ typedef enum { TC_FP32 = 0, TC_BF16 = 1, TC_FP8_E4M3 = 2 } tc_precision;
 
 /* Network descriptor.  levels L in [1, 8]; ch[l-1] = channels of pyramid
  * level l (multiples of 8, at most 128); dec = widths of the three decoder
- * conv layers (multiples of 16, at most 128); radius = cost-volume radius
+ * conv layers (multiples of 16, at most 128, with dec[1] + dec[2] <= 128:
+ * the head's input [h2 | h3]); radius = cost-volume radius
  * (4 gives 81 displacements); leaky = LeakyReLU slope.
  * Variants of Sec. 3.2 ("Optimized Network Architecture"): finest = the
  * finest level with a flow estimator, in [1, L] (1: every level; 2: the

@@ -30,6 +30,7 @@ struct tc_net {
 namespace {
 
 constexpr int kMaxN = 4096, kMaxHW = 16384;
+constexpr int kHeadMaxIn = 128;  // 16 channel blocks of 8 (launch_head)
 constexpr size_t kAlign = 256;
 
 #define TC_TRY_HIP(x)                        \
@@ -62,7 +63,8 @@ bool desc_ok(const tc_net_desc* d) {
     if (d->ch[l] <= 0 || d->ch[l] % 8 || d->ch[l] > 128) return false;
   for (int i = 0; i < 3; ++i)
     if (d->dec[i] <= 0 || d->dec[i] % 16 || d->dec[i] > 128) return false;
-  if ((d->dec[1] + d->dec[2]) % 8) return false;
+  // the estimator head (vector ALUs) takes at most kHeadMaxIn input channels
+  if ((d->dec[1] + d->dec[2]) % 8 || d->dec[1] + d->dec[2] > kHeadMaxIn) return false;
   if (d->radius != 4) return false;
   if (!(d->leaky >= 0.f && d->leaky <= 1.f)) return false;
   if (d->finest < 1 || d->finest > d->levels) return false;

@@ -45,8 +45,10 @@ class StreamJob:
     arrivals: np.ndarray
     alpha: float = 0.5
     keep_outputs: bool = False
+    keep_flows: bool = False
     # filled by the server
     outputs: list = field(default_factory=list)
+    flows: list = field(default_factory=list)  # (flow_fw, flow_bw) of frames 1, 2, ...
     latencies_ms: list = field(default_factory=list)
 
     @property
@@ -290,6 +292,8 @@ class Server:
                 r = g["slots"][sid]
                 if j.keep_outputs:
                     j.outputs.append(r.out[r.t % 2].clone())
+                if j.keep_flows and r.t > 0:
+                    j.flows.append((r.fw.clone(), r.bw.clone()))
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record()
                 out.append((j, k, ev))

@@ -113,6 +113,8 @@ class FallbackFlow:
         self.frames = 0
 
     def __call__(self, prev, cur):
+        if prev.shape[0] != 1:
+            raise ValueError("FallbackFlow decides per pair: one pair (n = 1) per call")
         fw, bw = self.student.flow_estimate_pair(prev, cur)
         tcflow.flow_agreement(fw, bw, counts=self.counts)
         agree = int(self.counts.item()) / float(self.h * self.w)   # host sync: the decision

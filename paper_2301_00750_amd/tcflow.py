@@ -166,6 +166,25 @@ def _frames(t, name, ch):
     return t
 
 
+def _out(t, name, shape, device, dtype=torch.float32):
+    """A caller-supplied output: `shape`, `dtype`, contiguous, on `device`
+    (the C ABI takes no size for outputs, so a short buffer would be written
+    past its end)."""
+    if not (isinstance(t, torch.Tensor) and t.dtype == dtype and t.is_contiguous()
+            and t.device == device and tuple(t.shape) == tuple(shape)):
+        raise ValueError(f"{name}: expected a contiguous {dtype} tensor of shape {tuple(shape)} "
+                         f"on {device}")
+    return t
+
+
+def _buffer(t, name, nbytes, device):
+    """A caller-supplied byte buffer (pyramid, workspace) of at least nbytes."""
+    if not (isinstance(t, torch.Tensor) and t.is_contiguous() and t.device == device
+            and t.numel() * t.element_size() >= nbytes):
+        raise ValueError(f"{name}: expected a contiguous buffer of >= {nbytes} bytes on {device}")
+    return t
+
+
 def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
@@ -222,10 +241,17 @@ class Net:
     def flow_from_pyramids(self, pyr1, pyr2, n, h, w, both=True, ws=None, out12=None, out21=None,
                            stream=None):
         dev = pyr1.device
+        pb = self.pyramid_bytes(n, h, w)
+        _buffer(pyr1, "pyr1", pb, dev)
+        _buffer(pyr2, "pyr2", pb, dev)
         if ws is None:
             ws = _workspace(self.decoder_workspace_bytes(n, h, w), dev)
-        f12 = out12 if out12 is not None else torch.empty(n, 2, h, w, device=dev)
-        f21 = (out21 if out21 is not None else torch.empty(n, 2, h, w, device=dev)) if both else None
+        f12 = (_out(out12, "out12", (n, 2, h, w), dev) if out12 is not None
+               else torch.empty(n, 2, h, w, device=dev))
+        f21 = None
+        if both:
+            f21 = (_out(out21, "out21", (n, 2, h, w), dev) if out21 is not None
+                   else torch.empty(n, 2, h, w, device=dev))
         _check("tc_flow_from_pyramids", _lib.tc_flow_from_pyramids(
             self._h, _ptr(pyr1), _ptr(pyr2), n, h, w, _ptr(f12), _ptr(f21), _ptr(ws),
             ws.numel() * ws.element_size(), _stream(stream)))
@@ -238,6 +264,15 @@ class Net:
         """One batched decoder pass over per-stream one-image pyramids
         (tc_flow_from_pyramid_list); fw[i], bw[i] are 1 x 2 x h x w outputs."""
         n = len(pyr_prev)
+        if not (len(pyr_cur) == len(fw) == len(bw) == n):
+            raise ValueError("pyr_prev, pyr_cur, fw and bw differ in length")
+        dev = ws.device
+        pb = self.pyramid_bytes(1, h, w)
+        for i in range(n):
+            _buffer(pyr_prev[i], f"pyr_prev[{i}]", pb, dev)
+            _buffer(pyr_cur[i], f"pyr_cur[{i}]", pb, dev)
+            _out(fw[i], f"fw[{i}]", (1, 2, h, w), dev)
+            _out(bw[i], f"bw[{i}]", (1, 2, h, w), dev)
         arr = ctypes.c_void_p * n
         _check("tc_flow_from_pyramid_list", _lib.tc_flow_from_pyramid_list(
             self._h, arr(*[p.data_ptr() for p in pyr_prev]), arr(*[p.data_ptr() for p in pyr_cur]),
@@ -257,8 +292,7 @@ class Net:
         n, _, h, w = prev.shape
         if ws is None:
             ws = _workspace(self.flow_half_workspace_bytes(n, h, w), prev.device)
-        fw = out_fw if out_fw is not None else torch.empty(n, 2, h, w, device=prev.device)
-        bw = out_bw if out_bw is not None else torch.empty(n, 2, h, w, device=prev.device)
+        fw, bw = self._pair_outputs(out_fw, out_bw, n, h, w, prev.device)
         _check("tc_flow_estimate_pair_half", _lib.tc_flow_estimate_pair_half(
             self._h, _ptr(prev), _ptr(cur), n, h, w, _ptr(fw), _ptr(bw), _ptr(ws),
             ws.numel() * ws.element_size(), _stream(stream)))
@@ -272,7 +306,8 @@ class Net:
         n, _, h, w = prev.shape
         if ws is None:
             ws = _workspace(self.flow_workspace_bytes(n, h, w), prev.device)
-        f = out if out is not None else torch.empty(n, 2, h, w, device=prev.device)
+        f = (_out(out, "out", (n, 2, h, w), prev.device) if out is not None
+             else torch.empty(n, 2, h, w, device=prev.device))
         _check("tc_flow_estimate", _lib.tc_flow_estimate(
             self._h, _ptr(prev), _ptr(cur), n, h, w, _ptr(f), _ptr(ws),
             ws.numel() * ws.element_size(), _stream(stream)))
@@ -286,11 +321,18 @@ class Net:
         n, _, h, w = prev.shape
         if ws is None:
             ws = _workspace(self.flow_workspace_bytes(n, h, w), prev.device)
-        fw = out_fw if out_fw is not None else torch.empty(n, 2, h, w, device=prev.device)
-        bw = out_bw if out_bw is not None else torch.empty(n, 2, h, w, device=prev.device)
+        fw, bw = self._pair_outputs(out_fw, out_bw, n, h, w, prev.device)
         _check("tc_flow_estimate_pair", _lib.tc_flow_estimate_pair(
             self._h, _ptr(prev), _ptr(cur), n, h, w, _ptr(fw), _ptr(bw), _ptr(ws),
             ws.numel() * ws.element_size(), _stream(stream)))
+        return fw, bw
+
+    @staticmethod
+    def _pair_outputs(out_fw, out_bw, n, h, w, device):
+        fw = (_out(out_fw, "out_fw", (n, 2, h, w), device) if out_fw is not None
+              else torch.empty(n, 2, h, w, device=device))
+        bw = (_out(out_bw, "out_bw", (n, 2, h, w), device) if out_bw is not None
+              else torch.empty(n, 2, h, w, device=device))
         return fw, bw
 
 
@@ -305,7 +347,8 @@ def consistency_step(stylized, prev_out, flow_fw, flow_bw, alpha, out=None, mask
     for t in (prev_out, flow_fw, flow_bw):
         if t.shape[0] != n or t.shape[2:] != stylized.shape[2:]:
             raise ValueError("consistency_step: shapes differ")
-    o = out if out is not None else torch.empty_like(stylized)
+    o = (_out(out, "out", (n, 3, h, w), stylized.device) if out is not None
+         else torch.empty_like(stylized))
     m = torch.empty(n, h, w, dtype=torch.uint8, device=stylized.device) if mask else None
     _check("tc_consistency_step", _lib.tc_consistency_step(
         _ptr(stylized), _ptr(prev_out), _ptr(flow_fw), _ptr(flow_bw), float(alpha), n, h, w,
@@ -321,7 +364,8 @@ def flow_agreement(flow_fw, flow_bw, counts=None, stream=None):
     n, _, h, w = flow_fw.shape
     if flow_bw.shape != flow_fw.shape:
         raise ValueError("flow_agreement: shapes differ")
-    c = counts if counts is not None else torch.empty(n, dtype=torch.int32, device=flow_fw.device)
+    c = (_out(counts, "counts", (n,), flow_fw.device, torch.int32) if counts is not None
+         else torch.empty(n, dtype=torch.int32, device=flow_fw.device))
     _check("tc_flow_agreement", _lib.tc_flow_agreement(_ptr(flow_fw), _ptr(flow_bw), n, h, w,
                                                        _ptr(c), _stream(stream)))
     return c
@@ -362,7 +406,7 @@ def consistency_paper(I_prev, I, I_next, P_prev, P, P_next, O_prev, flow_t_prev,
     prm = params if params is not None else paper_params()
     if ws is None:
         ws = _workspace(_lib.tc_paper_workspace_bytes(n, h, w), I.device)
-    o = out if out is not None else torch.empty_like(I)
+    o = _out(out, "out", (n, 3, h, w), I.device) if out is not None else torch.empty_like(I)
     _check("tc_consistency_paper", _lib.tc_consistency_paper(
         _ptr(I_prev), _ptr(I), _ptr(I_next), _ptr(P_prev), _ptr(P), _ptr(P_next), _ptr(O_prev),
         _ptr(flow_t_prev), _ptr(flow_t_next), ctypes.byref(prm), n, h, w, _ptr(o), _ptr(ws),

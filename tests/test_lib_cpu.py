@@ -105,6 +105,16 @@ def test_flow_argument_checks(tc):
     assert L.tc_flow_workspace_bytes(None, 1, 8, 8) == 0
 
 
+def test_head_width_limit(tc):
+    """The head's input [h2 | h3] is limited to 128 channels (16 blocks of 8
+    on the vector-ALU head): a wider descriptor is rejected at creation."""
+    d = dict(synth.load_desc("tiny"), dec=[96, 96, 48])
+    cd = tc.NetDesc.from_dict(d)
+    assert tc.lib().tc_weight_floats(ctypes.byref(cd)) == 0
+    ok = dict(synth.load_desc("tiny"), dec=[96, 96, 32])
+    assert tc.lib().tc_weight_floats(ctypes.byref(tc.NetDesc.from_dict(ok))) > 0
+
+
 def test_fp8_encoder_matches_torch_e4m3fn(tc):
     """The host FP8 encoder of the weights equals torch's float8_e4m3fn cast
     (round to nearest even) on normal, subnormal, tie and boundary values;
