@@ -39,7 +39,9 @@ typedef enum {
   TC_ERR_SHAPE = 2,       /* descriptor or weight count inconsistent           */
   TC_ERR_WORKSPACE = 3,   /* workspace / pyramid buffer too small or unaligned */
   TC_ERR_UNSUPPORTED = 4, /* precision or size this build does not handle      */
-  TC_ERR_HIP = 5          /* a HIP runtime call or kernel launch failed        */
+  TC_ERR_HIP = 5,         /* a HIP runtime call or kernel launch failed        */
+  TC_ERR_SCRATCH = 6      /* input too large for the static scratch of
+                             tc_flow_estimate_pair_noalloc                      */
 } tc_status;
 
 typedef enum { TC_FP32 = 0, TC_BF16 = 1, TC_FP8_E4M3 = 2 } tc_precision;
@@ -155,6 +157,28 @@ TC_API int tc_flow_estimate(const tc_net* net, const float* prev, const float* c
 TC_API int tc_flow_estimate_pair(const tc_net* net, const float* prev, const float* cur, int n,
                                  int h, int w, float* flow_fw, float* flow_bw, void* ws,
                                  size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * tc_flow_estimate_pair without a workspace argument.  The scratch (two
+ * pyramids and the decoder buffers) is a static device array of
+ * TC_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends; the call itself allocates nothing.  The inputs and outputs
+ * are as for tc_flow_estimate_pair and stay caller-owned.  Returns
+ * TC_ERR_SCRATCH, before enqueueing anything, when
+ * tc_flow_workspace_bytes(net, n, h, w) > TC_NOALLOC_SCRATCH_BYTES (e.g. the
+ * 5-level 16..128-channel FP32 network fits up to about 640 x 360 per pair).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams or host threads without ordering) race and give
+ * undefined results; calls ordered on one stream are safe.  The array keeps
+ * the last call's contents; nothing the kernels read is assumed to start at
+ * zero (what must be zero, e.g. the FP8 scale slots, is cleared by a kernel
+ * at the start of each call).  The device is the stream's (the current
+ * device for the NULL stream); the net must live on it. */
+#define TC_NOALLOC_SCRATCH_BYTES (256u << 20)
+TC_API int tc_flow_estimate_pair_noalloc(const tc_net* net, const float* prev, const float* cur,
+                                         int n, int h, int w, float* flow_fw, float* flow_bw,
+                                         void* stream);
 
 /* Flow pair of the paper's fast preset (Sec. 4.1, implementation details:
  * optical flow computed on half-sized inputs).  Each frame is reduced to

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -625,6 +626,8 @@ const char* tc_status_str(int st) {
     case TC_ERR_WORKSPACE: return "workspace too small or misaligned";
     case TC_ERR_UNSUPPORTED: return "unsupported precision or size";
     case TC_ERR_HIP: return "HIP runtime or launch error";
+    case TC_ERR_SCRATCH:
+      return "input needs more than the no-allocation entry point's static scratch";
     default: return "unknown status";
   }
 }
@@ -956,6 +959,57 @@ int tc_flow_estimate_pair(const tc_net* net, const float* prev, const float* cur
                           void* stream) {
   if (!flow_bw) return TC_ERR_INVALID_ARG;
   return flow_common(net, prev, cur, n, h, w, flow_fw, flow_bw, ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+// ---- the no-allocation entry point's scratch: one static array per device
+// (every GPU the library runs on holds its own copy until the process ends).
+// Host code never uses the array's name as an address: each device's address
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address reaches kernels.
+namespace {
+static __device__ __align__(256) unsigned char scratch[TC_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for(hipStream_t s, void** out) {
+  int dev = -1;
+  if (s) {
+    if (hipStreamGetDevice(s, &dev) != hipSuccess) return TC_ERR_HIP;
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    return TC_ERR_HIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return TC_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return TC_ERR_HIP;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return TC_ERR_HIP;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr) return TC_ERR_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int tc_flow_estimate_pair_noalloc(const tc_net* net, const float* prev, const float* cur, int n,
+                                  int h, int w, float* flow_fw, float* flow_bw, void* stream) {
+  if (!net || !prev || !cur || !flow_fw || !flow_bw || !shape_ok(n, h, w))
+    return TC_ERR_INVALID_ARG;
+  const size_t need = tc_flow_workspace_bytes(net, n, h, w);
+  if (need > (size_t)TC_NOALLOC_SCRATCH_BYTES) return TC_ERR_SCRATCH;
+  void* ptr = nullptr;
+  const int st = scratch_for((hipStream_t)stream, &ptr);
+  if (st) return st;
+  return flow_common(net, prev, cur, n, h, w, flow_fw, flow_bw, ptr, need, stream);
 }
 
 size_t tc_flow_half_workspace_bytes(const tc_net* net, int n, int h, int w) {

@@ -16,7 +16,10 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtcflow.so")
 
-TC_OK, TC_ERR_INVALID_ARG, TC_ERR_SHAPE, TC_ERR_WORKSPACE, TC_ERR_UNSUPPORTED, TC_ERR_HIP = range(6)
+(TC_OK, TC_ERR_INVALID_ARG, TC_ERR_SHAPE, TC_ERR_WORKSPACE, TC_ERR_UNSUPPORTED, TC_ERR_HIP,
+ TC_ERR_SCRATCH) = range(7)
+# static scratch of tc_flow_estimate_pair_noalloc (TC_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 256 << 20
 TC_FP32, TC_BF16, TC_FP8_E4M3 = 0, 1, 2
 
 EXPORTS = (
@@ -29,6 +32,7 @@ EXPORTS = (
     "tc_train_default_params", "tc_trainer_create", "tc_trainer_destroy", "tc_trainer_grad",
     "tc_trainer_step", "tc_trainer_copy", "tc_trainer_steps_done", "tc_flow_agreement",
     "tc_flow_half_workspace_bytes", "tc_flow_estimate_pair_half", "tc_paper_preset_params",
+    "tc_flow_estimate_pair_noalloc",
 )
 
 TC_PRESET_FINAL, TC_PRESET_OBJECTIVE, TC_PRESET_FAST = 0, 1, 2
@@ -130,6 +134,7 @@ def _load():
         "tc_flow_half_workspace_bytes": (sz, [vp, ci, ci, ci]),
         "tc_flow_estimate_pair_half": (ci, [vp, vp, vp, ci, ci, ci, vp, vp, vp, sz, vp]),
         "tc_paper_preset_params": (ci, [ci, ctypes.POINTER(PaperParams)]),
+        "tc_flow_estimate_pair_noalloc": (ci, [vp, vp, vp, ci, ci, ci, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -326,6 +331,22 @@ class Net:
             self._h, _ptr(prev), _ptr(cur), n, h, w, _ptr(fw), _ptr(bw), _ptr(ws),
             ws.numel() * ws.element_size(), _stream(stream)))
         return fw, bw
+
+    def flow_estimate_pair_noalloc(self, prev, cur, out_fw, out_bw, stream=None):
+        """tc_flow_estimate_pair_noalloc: the flow pair with the library's
+        static per-device scratch instead of a workspace.  The outputs are
+        caller-owned (nothing is allocated here either); calls that overlap
+        on one GPU race on the shared scratch."""
+        _frames(prev, "prev", 3)
+        _frames(cur, "cur", 3)
+        if prev.shape != cur.shape:
+            raise ValueError("prev and cur differ in shape")
+        n, _, h, w = prev.shape
+        _out(out_fw, "out_fw", (n, 2, h, w), prev.device)
+        _out(out_bw, "out_bw", (n, 2, h, w), prev.device)
+        _check("tc_flow_estimate_pair_noalloc", _lib.tc_flow_estimate_pair_noalloc(
+            self._h, _ptr(prev), _ptr(cur), n, h, w, _ptr(out_fw), _ptr(out_bw), _stream(stream)))
+        return out_fw, out_bw
 
     @staticmethod
     def _pair_outputs(out_fw, out_bw, n, h, w, device):

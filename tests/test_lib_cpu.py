@@ -61,8 +61,9 @@ def test_weight_floats_matches_generator(tc, name):
 
 
 def test_status_strings(tc):
-    for st in range(6):
+    for st in range(7):
         assert tc.lib().tc_status_str(st)
+    assert tc.lib().tc_status_str(tc.TC_ERR_SCRATCH) != tc.lib().tc_status_str(99)
     assert b"gfx950" in tc.lib().tc_version()
 
 
@@ -103,6 +104,17 @@ def test_flow_argument_checks(tc):
     assert L.tc_flow_estimate(None, p, p, 1, 8, 8, p, p, 1 << 20, None) == tc.TC_ERR_INVALID_ARG
     assert L.tc_pyramid_bytes(None, 1, 8, 8) == 0
     assert L.tc_flow_workspace_bytes(None, 1, 8, 8) == 0
+
+
+def test_noalloc_argument_checks(tc):
+    """tc_flow_estimate_pair_noalloc rejects null pointers and bad sizes
+    before touching the device; its scratch size is the header's."""
+    L = tc.lib()
+    p = ctypes.c_void_p(256)
+    assert L.tc_flow_estimate_pair_noalloc(None, p, p, 1, 8, 8, p, p, None) == tc.TC_ERR_INVALID_ARG
+    txt = open(os.path.join(ROOT, "include", "tcflow.h")).read()
+    m = re.search(r"#define TC_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == tc.NOALLOC_SCRATCH_BYTES
 
 
 def test_head_width_limit(tc):
