@@ -223,7 +223,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--frames", type=int, default=60)
     ap.add_argument("--cpu-frames", type=int, default=2,
-                    help="frames of the workload the FP64 oracle is timed on (0 = skip)")
+                    help="frames of the workload the FP64 oracle is timed on (0 = skip the oracle)")
+    ap.add_argument("--epe-frames", type=int, default=8,
+                    help="frames, spread over the sequence, on which every form's flows and "
+                         "outputs are compared with the oracle")
+    ap.add_argument("--cpu-single", type=int, default=0,
+                    help="also time one 1080p oracle frame on one thread (minutes)")
+    ap.add_argument("--gt-frames", type=int, default=2,
+                    help="frames on which the consistency step runs on ground-truth flows "
+                         "(alpha sweep vs the oracle, kernel bandwidth; 0 = skip)")
     ap.add_argument("--forms", default="bf16,fp8",
                     help="comma-separated precision forms measured after the FP32 path ('' = none)")
     ap.add_argument("--paper-steps", type=int, default=30,
@@ -384,13 +392,24 @@ def main():
     if args.serve_frames > 0:
         result["serving"] = serve_leg(tcflow, desc, blob, args.serve_frames)
 
+    if args.gt_frames > 0:
+        log("consistency step on ground-truth flows")
+        gt_t = [int(round(x)) for x in np.linspace(1, args.frames - 1, args.gt_frames)]
+        result["consistency_gt_flows"] = consistency_gt_leg(tcflow, scene, I, P, gt_t)
+
     if args.cpu_frames > 0:
-        result["cpu_baseline"], epe = cpu_leg(nets, desc, I, P, args.cpu_frames)
+        result["cpu_baseline"], epe = cpu_leg(nets, desc, I, P, args.cpu_frames,
+                                              max(args.cpu_frames, args.epe_frames))
+        result["cpu_baseline"]["tiny_128x96"] = tiny_oracle_leg()
+        if args.cpu_single:
+            log("oracle frame on one thread")
+            result["cpu_baseline"]["single_thread_s_per_frame"] = round(
+                single_thread_frame(desc, I, P), 2)
         result["epe_vs_oracle"] = epe.pop("fp32")
         for form, e in epe.items():
             result["precision_forms"][form]["epe_vs_oracle"] = e
         for vname, v in variants.items():
-            _, vepe = cpu_leg(v["nets"], v["desc"], I, P, 1)
+            _, vepe = cpu_leg(v["nets"], v["desc"], I, P, 1, 1)
             for form, e in vepe.items():
                 result["variants"][vname][form]["epe_vs_oracle"] = e
     print(json.dumps(result), flush=True)
@@ -713,58 +732,188 @@ def paper_leg(tcflow, net, I, P, steps, flow_ms):
     }
 
 
-def cpu_leg(nets, desc, I, P, nframes):
-    """Time the FP64 oracle on `nframes` frames of the same workload (flow
-    pair + consistency step with O_{t-1} = P_{t-1}) and compare each GPU
-    form's flows, and its consistency step on the oracle's flows, with it."""
+def epe_stats(g, r):
+    """(mean, p99, max) end-point error of GPU flow g (1 x 2 x h x w) against r."""
+    d = g[0].double().cpu().numpy() - r
+    e = np.sqrt((d ** 2).sum(0))
+    return float(e.mean()), float(np.percentile(e, 99)), float(e.max())
+
+
+def cpu_leg(nets, desc, I, P, ntimed, nepe):
+    """The FP64 oracle on frames spread over the sequence: flow pairs (both
+    pyramids) and the consistency step with O_{t-1} = P_{t-1}, alpha 0.5.
+    The first `ntimed` frames are timed on the host's BLAS threads
+    (cpu_baseline).  Per precision form: EPE of its flows (mean, p99, max
+    over frames and directions), and its consistency step on its own flows
+    against the oracle's step on the oracle's flows (output max / RMS error,
+    fraction of pixels whose visibility decision differs); for FP32 also the
+    consistency kernel alone on the oracle's flows."""
     from oracle import tcflow_oracle as O
     from paper_2301_00750_amd import tcflow
 
     wts = O.unpack_weights(synth.he_weights(desc), desc)
-    stats = {k: {"epe": [], "max": []} for k in nets}
-    oerr = []
-    cpu_s = 0.0
-    for t in range(1, nframes + 1):
-        gpu = {}
-        for k, net in nets.items():
-            gpu[k] = net.flow_estimate_pair(I[t - 1], I[t])
+    nf = len(I)
+    ts = sorted(set(int(round(x)) for x in np.linspace(1, nf - 1, max(1, nepe))))
+    stats = {k: {"epe": [], "p99": [], "max": [], "out_max": [], "out_rms": [], "flip": []}
+             for k in nets}
+    iso = []
+    cpu_s, timed = 0.0, 0
+    dev = I[0].device
+    for t in ts:
+        gpu = {k: net.flow_estimate_pair(I[t - 1], I[t]) for k, net in nets.items()}
         torch.cuda.synchronize()
         a64, b64 = I[t - 1][0].double().cpu().numpy(), I[t][0].double().cpu().numpy()
         p64, q64 = P[t][0].double().cpu().numpy(), P[t - 1][0].double().cpu().numpy()
         log(f"oracle frame {t}")
         c0 = time.perf_counter()
         rfw, rbw = O.flow_pair(a64, b64, wts, desc)
-        O.consistency(p64, q64, rfw, rbw, 0.5)
-        cpu_s += time.perf_counter() - c0
+        ro, rm, _, _ = O.consistency(p64, q64, rfw, rbw, 0.5)
+        if timed < ntimed:
+            cpu_s += time.perf_counter() - c0
+            timed += 1
         for k, (fw, bw) in gpu.items():
             for g, r in ((fw, rfw), (bw, rbw)):
-                d = g[0].double().cpu().numpy() - r
-                e = np.sqrt((d ** 2).sum(0))
-                stats[k]["epe"].append(float(e.mean()))
-                stats[k]["max"].append(float(e.max()))
-        # the GPU consistency step on the oracle's flows (rounded to float32)
-        dev = I[0].device
+                m, p99, mx = epe_stats(g, r)
+                stats[k]["epe"].append(m)
+                stats[k]["p99"].append(p99)
+                stats[k]["max"].append(mx)
+            go, gm = tcflow.consistency_step(P[t], P[t - 1], fw, bw, 0.5, mask=True)
+            d = go[0].double().cpu().numpy() - ro
+            stats[k]["out_max"].append(float(np.abs(d).max()))
+            stats[k]["out_rms"].append(float(np.sqrt((d ** 2).mean())))
+            stats[k]["flip"].append(float((gm[0].cpu().numpy().astype(bool) != rm).mean()))
+        # the GPU consistency step alone on the oracle's flows (rounded to float32)
         f32 = [torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32))[None].to(dev)
                for x in (rfw, rbw)]
         go = tcflow.consistency_step(P[t], P[t - 1], f32[0], f32[1], 0.5)
-        ro, _, margin, _ = O.consistency(p64, q64, rfw.astype(np.float32).astype(np.float64),
-                                         rbw.astype(np.float32).astype(np.float64), 0.5)
+        ro32, _, margin, _ = O.consistency(p64, q64, rfw.astype(np.float32).astype(np.float64),
+                                           rbw.astype(np.float32).astype(np.float64), 0.5)
         decided = np.abs(margin) > 1e-4
-        oerr.append(float(np.abs(go[0].double().cpu().numpy() - ro)[:, decided].max()))
+        iso.append(float(np.abs(go[0].double().cpu().numpy() - ro32)[:, decided].max()))
     base = {
-        "value": round(nframes / cpu_s, 5),
+        "value": round(timed / cpu_s, 5),
         "unit": "frames/s",
         "cores": blas_threads(),
         "kind": "oracle",
-        "sample": f"{nframes} frames of the 1920x1080 workload: FP64 flow pair (both pyramids) "
+        "sample": f"{timed} frames of the 1920x1080 workload: FP64 flow pair (both pyramids) "
                   f"+ consistency step, {cpu_s:.1f} s",
     }
     epe = {}
     for k, s_ in stats.items():
-        epe[k] = {"mean_px": max(s_["epe"]), "max_px": max(s_["max"]), "frames": nframes,
-                  "tolerance_mean_px": 0.05 if k == "fp32" else 0.25}
-    epe["fp32"]["consistency_max_abs"] = max(oerr)
+        epe[k] = {"mean_px": float(np.mean(s_["epe"])), "worst_frame_mean_px": max(s_["epe"]),
+                  "p99_px": max(s_["p99"]), "max_px": max(s_["max"]), "frames": ts,
+                  "tolerance_mean_px": 0.05 if k == "fp32" else 0.25,
+                  "output_vs_oracle": {"max_abs": max(s_["out_max"]), "rms": max(s_["out_rms"]),
+                                       "mask_flip_frac": max(s_["flip"]),
+                                       "note": "the form's consistency step on its own flows vs "
+                                               "the oracle's on the oracle's flows, alpha 0.5, "
+                                               "O_{t-1} = P_{t-1}; worst frame"}}
+    epe["fp32"]["consistency_max_abs"] = max(iso)
     return base, epe
+
+
+def tiny_oracle_leg():
+    """The oracle on the 128 x 96 pair (4-level net): seconds per flow pair +
+    consistency step on the host's BLAS threads, and on one thread."""
+    from oracle import tcflow_oracle as O
+    d = synth.load_desc("tiny")
+    wts = O.unpack_weights(synth.he_weights(d), d)
+    prev, cur, _, _ = synth.tiny_pair()
+    a, b = prev.double().numpy(), cur.double().numpy()
+    P0, P1 = synth.stylize(prev, 0).double().numpy(), synth.stylize(cur, 1).double().numpy()
+
+    def run():
+        c0 = time.perf_counter()
+        fw, bw = O.flow_pair(a, b, wts, d)
+        O.consistency(P1, P0, fw, bw, 0.5)
+        return time.perf_counter() - c0
+
+    run()
+    multi = min(run() for _ in range(3))
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            single = min(run() for _ in range(3))
+    except ImportError:
+        single = None
+    return {"workload": "128x96 pair, 4-level net 16/32/64/96: flow pair + consistency step",
+            "seconds": round(multi, 4), "cores": blas_threads(),
+            "single_thread_seconds": round(single, 4) if single is not None else None}
+
+
+def single_thread_frame(desc, I, P):
+    """One 1920x1080 frame of the oracle (flow pair + consistency) on one
+    BLAS thread (opt-in: minutes)."""
+    from oracle import tcflow_oracle as O
+    from threadpoolctl import threadpool_limits
+    wts = O.unpack_weights(synth.he_weights(desc), desc)
+    a, b = I[0][0].double().cpu().numpy(), I[1][0].double().cpu().numpy()
+    p, q = P[1][0].double().cpu().numpy(), P[0][0].double().cpu().numpy()
+    with threadpool_limits(limits=1):
+        c0 = time.perf_counter()
+        fw, bw = O.flow_pair(a, b, wts, desc)
+        O.consistency(p, q, fw, bw, 0.5)
+        return time.perf_counter() - c0
+
+
+def consistency_gt_leg(tcflow, scene, I, P, frames, launches=200):
+    """The consistency step at 1920x1080 on the scene's ground-truth flows,
+    where most pixels are visible: the alpha sweep against the oracle on
+    `frames` (one step each, O_{t-1} = P_{t-1}), and the kernel's time and
+    HBM bandwidth over `launches` launches in that regime."""
+    from oracle import tcflow_oracle as O
+    dev = I[0].device
+    res = {"alphas": list(ALPHAS), "frames": list(frames)}
+    errs, vis, amb_frac = [], [], []
+    mismatch = 0
+    for t in frames:
+        ffw = scene.gt_flow(t - 1, t, device=dev)[0][None].contiguous()
+        fbw = scene.gt_flow(t, t - 1, device=dev)[0][None].contiguous()
+        p64, q64 = P[t][0].double().cpu().numpy(), P[t - 1][0].double().cpu().numpy()
+        f64 = ffw[0].double().cpu().numpy(), fbw[0].double().cpu().numpy()
+        for a in ALPHAS:
+            go, gm = tcflow.consistency_step(P[t], P[t - 1], ffw, fbw, a, mask=True)
+            ro, rm, margin, G = O.consistency(p64, q64, f64[0], f64[1], a)
+            gm = gm[0].cpu().numpy().astype(bool)
+            fa = O.warp_clamp(f64[0], f64[1])
+            scale = 1 + (f64[1] ** 2).sum(0) + (fa ** 2).sum(0) + ((f64[1] + fa) ** 2).sum(0)
+            amb = np.abs(margin) <= 1e-5 * scale
+            mismatch += int((gm[~amb] != rm[~amb]).sum())
+            alt = np.where(gm[None], (1 - a) * p64 + a * G, p64)
+            errs.append(float(np.abs(go[0].double().cpu().numpy() - alt).max()))
+            vis.append(float(gm.mean()))
+            amb_frac.append(float(amb.mean()))
+    res["max_abs_vs_oracle"] = max(errs)
+    res["visible_frac"] = round(float(np.mean(vis)), 5)
+    res["undecided_frac"] = max(amb_frac)
+    res["decided_pixels_differing"] = mismatch
+    # timing in the visible regime
+    t = frames[0]
+    ffw = scene.gt_flow(t - 1, t, device=dev)[0][None].contiguous()
+    fbw = scene.gt_flow(t, t - 1, device=dev)[0][None].contiguous()
+    out = torch.empty_like(P[t])
+    for _ in range(10):
+        tcflow.consistency_step(P[t], P[t - 1], ffw, fbw, 0.5, out=out)
+    torch.cuda.synchronize()
+    probe = tcflow.Probe(tcflow.TC_STAGE_CONSISTENCY, launches)
+    for i in range(launches):
+        tcflow.consistency_step(P[t], P[t - 1], ffw, fbw, ALPHAS[i % len(ALPHAS)], out=out)
+    n, ms = probe.read()
+    probe.close()
+    _, gm = tcflow.consistency_step(P[t], P[t - 1], ffw, fbw, 0.5, mask=True)
+    vf = float(gm.float().mean())
+    px = out.shape[2] * out.shape[3]
+    # bytes moved: P 12, f_bw 8, f_fw 8 (gathered near the pixel), out 12, and
+    # O_{t-1} 12 where the pixel is visible (the warp is skipped elsewhere)
+    bpp = 40.0 + 12.0 * vf
+    avg_ms = ms / max(1, n)
+    gbs = bpp * px / (avg_ms * 1e-3) / 1e9
+    res["kernel"] = {"name": "consistency_kernel", "avg_launch_us": round(1e3 * avg_ms, 3),
+                     "launches": n, "visible_frac": round(vf, 5),
+                     "bytes_per_px": round(bpp, 3), "achieved_GBps": round(gbs, 1),
+                     "peak_GBps": PEAK_HBM, "frac": round(gbs / PEAK_HBM, 4),
+                     "algorithmic_bytes_per_px": 52}
+    return res
 
 
 if __name__ == "__main__":

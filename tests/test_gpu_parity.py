@@ -333,7 +333,18 @@ def test_fp32_winograd_batch_invariance_and_determinism(tc):
 #
 # Convolutions and the cost volume read BF16 activations and weights and
 # accumulate in FP32; flows, upsampling, warp coordinates and the flow
-# accumulation stay FP32.  Bar: mean EPE <= 0.25 px against the FP64 oracle.
+# accumulation stay FP32.  Bar: mean EPE <= 0.25 px against the FP64 oracle
+# (the stated tolerance).  Regression guards beside it: mean <= 0.05 px and
+# max <= 0.3 px (an 8-bit mantissa gives ~2^-9 relative error per rounded
+# operand; measured at 1080p 0.015 / 0.057 px BF16, 0.020 / 0.086 px FP8).
+LP_BARS = dict(mean=0.25, guard_mean=0.05, guard_max=0.3)
+
+
+def check_lowp(name, a, b):
+    mean, mx = flow_err(a, b)
+    say(f"   {name}: EPE mean={mean:.3e} max={mx:.3e}")
+    assert mean <= LP_BARS["mean"]
+    assert mean <= LP_BARS["guard_mean"] and mx <= LP_BARS["guard_max"]
 
 
 @pytest.mark.parametrize("levels", [1, 4])
@@ -348,9 +359,7 @@ def test_bf16_flow_tiny_vs_oracle(tc, levels):
     torch.cuda.synchronize()
     rfw, rbw = O.flow_pair(f64(prev), f64(cur), wts, d)
     for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
-        mean, mx = flow_err(a, b)
-        say(f"   {name}: EPE mean={mean:.3e} max={mx:.3e}")
-        assert mean <= 0.25
+        check_lowp(name, a, b)
 
 
 def test_bf16_batch_invariance_and_determinism(tc, tiny):
@@ -379,9 +388,7 @@ def test_bf16_fullhd_pair_vs_oracle(tc):
     torch.cuda.synchronize()
     rfw, rbw = O.flow_pair(f64(I0), f64(I1), wts, d)
     for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
-        mean, mx = flow_err(a, b)
-        say(f"   {name}: EPE mean={mean:.3e} max={mx:.3e}")
-        assert mean <= 0.25
+        check_lowp(name, a, b)
 
 
 # ---------------------------------------------------------------- the paper's consistency step
@@ -458,9 +465,7 @@ def test_fp8_flow_tiny_vs_oracle(tc, levels):
     torch.cuda.synchronize()
     rfw, rbw = O.flow_pair(f64(prev), f64(cur), wts, d)
     for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
-        mean, mx = flow_err(a, b)
-        say(f"   {name}: EPE mean={mean:.3e} max={mx:.3e}")
-        assert mean <= 0.25
+        check_lowp(name, a, b)
 
 
 def test_fp8_batch_invariance_and_determinism(tc, tiny):
@@ -489,6 +494,4 @@ def test_fp8_fullhd_pair_vs_oracle(tc):
     torch.cuda.synchronize()
     rfw, rbw = O.flow_pair(f64(I0), f64(I1), wts, d)
     for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
-        mean, mx = flow_err(a, b)
-        say(f"   {name}: EPE mean={mean:.3e} max={mx:.3e}")
-        assert mean <= 0.25
+        check_lowp(name, a, b)
