@@ -232,8 +232,10 @@ def main():
     ap.add_argument("--gt-frames", type=int, default=2,
                     help="frames on which the consistency step runs on ground-truth flows "
                          "(alpha sweep vs the oracle, kernel bandwidth; 0 = skip)")
-    ap.add_argument("--forms", default="bf16,fp8",
-                    help="comma-separated precision forms measured after the FP32 path ('' = none)")
+    ap.add_argument("--forms", default="bf16,fp8,bf16_bf16feat",
+                    help="comma-separated precision forms measured after the FP32 path ('' = none); "
+                         "bf16_bf16feat = the BF16 form with bfloat16 pyramid features (cost "
+                         "volume on bfloat16 inputs, float32 products)")
     ap.add_argument("--paper-steps", type=int, default=30,
                     help="1080p frames of the paper's full consistency step to time (0 = skip)")
     ap.add_argument("--serve-frames", type=int, default=300,
@@ -352,12 +354,13 @@ def main():
     forms = {}
     nets = {"fp32": r["net"]}
     for form in [f for f in args.forms.split(",") if f]:
-        prec = {"bf16": tcflow.TC_BF16, "fp8": tcflow.TC_FP8_E4M3}[form]
+        prec = {"bf16": tcflow.TC_BF16, "fp8": tcflow.TC_FP8_E4M3,
+                "bf16_bf16feat": tcflow.TC_BF16 | tcflow.TC_PREC_BF16_FEATURES}[form]
         log(f"{form}: timing {K} steps")
         rf = measure(tcflow, desc, blob, prec, I, P, K, args.warmup, args.frames)
         log(f"{form}: {rf['fps']:.1f} frames/s, {rf['ms']:.3f} ms/frame")
         nets[form] = rf["net"]
-        peak = PEAK_BF16_MFMA if form == "bf16" else PEAK_FP8_MFMA
+        peak = PEAK_FP8_MFMA if form == "fp8" else PEAK_BF16_MFMA
         ach = c1_flops(desc, H, W) / (rf["c1_alone_ms"] * 1e-3) / 1e12
         forms[form] = {
             "value": round(rf["fps"], 2), "unit": "frames/s", "ms_per_step": round(rf["ms"], 4),
@@ -378,7 +381,8 @@ def main():
     for vname in [v for v in args.variants.split(",") if v]:
         vd = synth.load_desc(vname)
         variants[vname] = variant_leg(tcflow, vd, I, P, K, args.warmup, args.frames,
-                                      ["fp32"] + [f for f in args.forms.split(",") if f], r["fps"])
+                                      ["fp32"] + [f for f in args.forms.split(",")
+                                                  if f in ("bf16", "fp8")], r["fps"])
     if variants:
         result["variants"] = {k: v["report"] for k, v in variants.items()}
 
@@ -424,7 +428,8 @@ def variant_leg(tcflow, vdesc, I, P, K, W, frames, forms, base_fps):
     f = vdesc.get("finest", 1)
     has_ref = bool((vdesc.get("refine") or {}).get("ch"))
     stage = tcflow.stage_id(f, tcflow.TC_OP_REFINE if has_ref else tcflow.TC_OP_C1)
-    precs = {"fp32": tcflow.TC_FP32, "bf16": tcflow.TC_BF16, "fp8": tcflow.TC_FP8_E4M3}
+    precs = {"fp32": tcflow.TC_FP32, "bf16": tcflow.TC_BF16, "fp8": tcflow.TC_FP8_E4M3,
+             "bf16_bf16feat": tcflow.TC_BF16 | tcflow.TC_PREC_BF16_FEATURES}
     report, nets = {"finest": f, "refine": vdesc.get("refine")}, {}
     for form in forms:
         log(f"variant {vdesc['name']} {form}: timing {K} steps")

@@ -45,6 +45,11 @@ typedef enum {
 } tc_status;
 
 typedef enum { TC_FP32 = 0, TC_BF16 = 1, TC_FP8_E4M3 = 2 } tc_precision;
+/* OR-ed into the precision of TC_BF16 or TC_FP8_E4M3 nets: store the pyramid
+ * features (the cost volume's inputs) as bfloat16 instead of float16, and
+ * correlate them in float32 (the form measured beside the float16 cost
+ * volume). */
+#define TC_PREC_BF16_FEATURES 0x100
 
 /* Network descriptor.  levels L in [1, 8]; ch[l-1] = channels of pyramid
  * level l (multiples of 8, at most 128); dec = widths of the three decoder
@@ -94,10 +99,15 @@ TC_API size_t tc_weight_floats(const tc_net_desc* desc);
  * (BF16 activations and weights, FP32 accumulation); TC_FP8_E4M3 (BF16
  * activations rounded to FP8 with a per-image, per-tensor scale max|x| / 448
  * when a conv stages them, FP8 weights with per-output-channel scales, FP32
- * accumulation).  In every form the flows, their upsampling and accumulation
- * and the warp coordinates are FP32, and the cost volume accumulates in FP32.  Paper, Sec. 3.2: PWC-Net-shaped network with
- * light estimators (a conv feature pyramid, warping, correlation and a CNN
- * flow estimator per level).  *out is set only on TC_OK. */
+ * accumulation).  In the BF16 and FP8 forms the pyramid features are stored
+ * as float16 (bfloat16 with TC_PREC_BF16_FEATURES): the cost volume warps and
+ * correlates them with float16 products and float32 sums, and the convs that
+ * read them convert to their operand type when staging.  In every form the
+ * flows, their upsampling and accumulation and the warp coordinates are FP32,
+ * and the cost volume accumulates in FP32.  Paper, Sec. 3.2: PWC-Net-shaped
+ * network with light estimators (a conv feature pyramid, warping, correlation
+ * and a CNN flow estimator per level).  *out is set only on TC_OK;
+ * TC_ERR_UNSUPPORTED for an unknown precision. */
 TC_API int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_floats,
                          int precision, tc_net** out);
 TC_API void tc_net_destroy(tc_net* net);

@@ -73,6 +73,47 @@ __device__ inline void store8(bf16* p, const float (&v)[8]) {
 __device__ inline void store1(float* p, float v) { *p = v; }
 __device__ inline void store1(bf16* p, float v) { *p = f2bf(v); }
 
+// float16 activations (the pyramid features of the BF16 and FP8 forms: the
+// cost volume's inputs), round to nearest even.
+typedef _Float16 f16;
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+__device__ inline unsigned pack2h(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(float2v{a, b}, h2));
+}
+
+__device__ inline void unpack8h(const u4& x, float (&v)[8]) {
+  const unsigned wd[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const h2 p = __builtin_bit_cast(h2, wd[k]);
+    v[2 * k] = (float)p.x;
+    v[2 * k + 1] = (float)p.y;
+  }
+}
+
+__device__ inline void load8(const f16* p, float (&v)[8]) {
+  unpack8h(*reinterpret_cast<const u4*>(p), v);
+}
+
+__device__ inline void load8g(const f16* p, float (&v)[8]) {
+  unpack8h(ldg(reinterpret_cast<const u4*>(p)), v);
+}
+
+__device__ inline void store8(f16* p, const float (&v)[8]) {
+  *reinterpret_cast<u4*>(p) =
+      u4{pack2h(v[0], v[1]), pack2h(v[2], v[3]), pack2h(v[4], v[5]), pack2h(v[6], v[7])};
+}
+
+__device__ inline void store1(f16* p, float v) { *p = (f16)v; }
+
+// 8 float16 values (one 16-byte word) -> 8 bfloat16 (round to nearest even).
+__device__ inline u4 h8_to_bf8(const u4& x) {
+  float v[8];
+  unpack8h(x, v);
+  return u4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
+}
+
 }  // namespace tc
 
 namespace tc {

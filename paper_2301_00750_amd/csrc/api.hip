@@ -19,6 +19,8 @@ struct tc_net {
   int precision;
   int bf16act;      // activations stored as bfloat16, convs on BF16 MFMA
   int fp8;          // convs on FP8 E4M3 MFMA (activations still stored as bfloat16)
+  int f16feat;      // BF16/FP8 forms: pyramid features stored as float16 (the
+                    // cost volume's inputs); the convs reading them convert
   int esz;          // bytes per stored activation element
   int ncv;          // (2r+1)^2
   int zcb;          // blocks of the cost-volume buffer (ncv + 2, rounded up to 8)
@@ -378,8 +380,11 @@ View plain_view(const float* p, int cbt, int cb0 = 0) {
 int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, int in_h, int in_w,
                float* out, int out_cbt, int out_cb0, int compact, const float* add, int out_h,
                int out_w, int relu, float slope, int n, int stride, int stage, float* partial,
-               int act_bf16, const AmaxIn* ain, unsigned* aout, hipStream_t s) {
+               int act_bf16, const AmaxIn* ain, unsigned* aout, hipStream_t s, int in_f16 = 0,
+               int out_f16 = 0) {
   ConvArgs a;
+  a.in_f16 = in_f16;
+  a.out_f16 = out_f16;
   a.in0 = in0;
   a.in1 = in1;
   a.nb0 = nb0;
@@ -459,15 +464,18 @@ int run_pyramid(const tc_net* net, const float* frames, int n, int h, int w, cha
                              {nullptr, nullptr, 0}, {nullptr, nullptr, 0}};
     const AmaxIn ain_b[3] = {amax_plain(slot(pyr_slot_tmp(l))), {nullptr, nullptr, 0},
                              {nullptr, nullptr, 0}};
+    // level l >= 2 reads the float16 features of level l - 1
+    const int fin = (l > 1 && net->f16feat) ? 1 : 0;
     int st = conv_layer(La, plain_view(in, in_cbt), La.cin_pad / ((La.bf16 || La.fp8) ? 8 : La.kc),
                         plain_view(in, in_cbt), in_h, in_w, tmp, C / 8, 0, 0, nullptr, g.h[l], g.w[l],
                         1, d.leaky, n, 2, TC_STAGE(l, TC_OP_PYR_A), part, net->bf16act, ain_a,
-                        nullptr, s);
+                        nullptr, s, fin, 0);
     if (st) return st;
     st = conv_layer(net->pyr[l - 1][1], plain_view(tmp, C / 8), C / 8, plain_view(tmp, C / 8),
                     g.h[l], g.w[l], feat, C / 8, 0, 0, nullptr, g.h[l], g.w[l], 1, d.leaky, n, 1,
                     TC_STAGE(l, TC_OP_PYR_B), part, net->bf16act, ain_b,
-                    net->dec[l - 1][0].fp8 ? slot(pyr_slot_feat(l)) : nullptr, s);
+                    net->dec[l - 1][0].fp8 ? slot(pyr_slot_feat(l)) : nullptr, s, 0,
+                    net->f16feat);
     if (st) return st;
     in = feat;
     in_cbt = C / 8;
@@ -548,6 +556,7 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
     cv.cps = cp.cps;
     cv.partial = part;
     cv.bf16act = net->bf16act;
+    cv.f16feat = net->f16feat;
     cv.aout = net->dec[l - 1][0].fp8 ? dslot(l, 0) : nullptr;
     probe_begin(TC_STAGE(l, TC_OP_COST_VOLUME), s);
     TC_TRY_HIP(launch_warp_cost_volume(cv, s));
@@ -559,9 +568,10 @@ int run_decoder(const tc_net* net, const char* pyr1, const char* pyr2, int n, in
     const AmaxIn ain_c1[3] = {fa, amax_plain(dslot(l, 0)), none};
     const AmaxIn ain_c2[3] = {amax_plain(dslot(l, 1)), none, none};
     const AmaxIn ain_c3[3] = {amax_plain(dslot(l, 2)), none, none};
+    // c1's K chunks: F1 (float16 features in the BF16/FP8 forms), then Z
     int st = conv_layer(L[0], f1, C / 8, plain_view(Z, net->zcb), hl, wl, H1, d0b, 0, 0, nullptr,
                         hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C1), part, net->bf16act,
-                        ain_c1, L[1].fp8 ? dslot(l, 1) : nullptr, s);
+                        ain_c1, L[1].fp8 ? dslot(l, 1) : nullptr, s, net->f16feat ? 1 : 0, 0);
     if (st) return st;
     st = conv_layer(L[1], plain_view(H1, d0b), d0b, plain_view(H1, d0b), hl, wl, H23, hcb, 0, 0,
                     nullptr, hl, wl, 1, d.leaky, nb, 1, TC_STAGE(l, TC_OP_C2), part, net->bf16act,
@@ -663,15 +673,18 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
                   int precision, tc_net** out) {
   if (!desc || !host_weights || !out) return TC_ERR_INVALID_ARG;
   if (!desc_ok(desc)) return TC_ERR_SHAPE;
-  if (precision != TC_FP32 && precision != TC_BF16 && precision != TC_FP8_E4M3)
+  const int base_prec = precision & ~TC_PREC_BF16_FEATURES;
+  if ((base_prec != TC_FP32 && base_prec != TC_BF16 && base_prec != TC_FP8_E4M3) ||
+      (base_prec == TC_FP32 && (precision & TC_PREC_BF16_FEATURES)))
     return TC_ERR_UNSUPPORTED;
   if (n_floats != tc_weight_floats(desc)) return TC_ERR_SHAPE;
   tc_net* net = new (std::nothrow) tc_net();
   if (!net) return TC_ERR_HIP;
   net->d = *desc;
   net->precision = precision;
-  net->bf16act = precision == TC_BF16 || precision == TC_FP8_E4M3;
-  net->fp8 = precision == TC_FP8_E4M3;
+  net->bf16act = base_prec == TC_BF16 || base_prec == TC_FP8_E4M3;
+  net->fp8 = base_prec == TC_FP8_E4M3;
+  net->f16feat = net->bf16act && !(precision & TC_PREC_BF16_FEATURES);
   net->esz = net->bf16act ? 2 : 4;
   net->ncv = (2 * desc->radius + 1) * (2 * desc->radius + 1);
   net->zcb = (net->ncv + 2 + 7) / 8;

@@ -575,15 +575,19 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
 
   u4 ra[RA];
   W rb[RB];
+  int rh = 0;  // bit j: ra[j] holds float16 values (converted when stashed)
   auto fetch = [&](int ch) {
+    rh = 0;
 #pragma unroll
     for (int j = 0; j < RA; ++j) {
       u4 val = u4{0u, 0u, 0u, 0u};
       const int b = ch * BF_CPC + f_cbi[j];
       if (f_off[j] >= 0 && b < nblk) {
-        const bf16* src = b < a.nb0 ? base0 + (size_t)(b + a.in0.cb0) * in_plane
-                                    : base1 + (size_t)(b - a.nb0 + a.in1.cb0) * in_plane;
+        const bool v0 = b < a.nb0;
+        const bf16* src = v0 ? base0 + (size_t)(b + a.in0.cb0) * in_plane
+                             : base1 + (size_t)(b - a.nb0 + a.in1.cb0) * in_plane;
         val = ldg(reinterpret_cast<const u4*>(src + (size_t)f_off[j] * 8));
+        rh |= ((a.in_f16 >> (v0 ? 0 : 1)) & 1) << j;
       }
       ra[j] = val;
     }
@@ -599,12 +603,16 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
     for (int j = 0; j < RA; ++j) {
       const int i = tid + j * 256;
       if (i < NA) {
+        const bool h = (rh >> j) & 1;
         if constexpr (F8) {
           float v[8];
-          load8(reinterpret_cast<const bf16*>(&ra[j]), v);
+          if (h)
+            unpack8h(ra[j], v);
+          else
+            load8(reinterpret_cast<const bf16*>(&ra[j]), v);
           sA[i] = pack8_fp8(v, inv_sa);
         } else {
-          sA[i] = ra[j];
+          sA[i] = h ? h8_to_bf8(ra[j]) : ra[j];
         }
       }
     }
@@ -672,7 +680,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
           float v = acc[mb][nb][vv] * osc + bn;
           if (a.lrelu) v = v >= 0.f ? v : a.slope * v;
           if (nok && oy < a.out_h && tx0 + px < a.out_w) mx = fmaxf(mx, fabsf(v));
-          so[px * NP + n] = f2bf(v);
+          so[px * NP + n] = a.out_f16 ? __builtin_bit_cast(bf16, (f16)v) : f2bf(v);
         }
       }
       __syncthreads();
@@ -709,7 +717,10 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
             const size_t pix = ((size_t)img * a.out_h + oy) * a.out_w + ox;
             const float v = finish(a, accv, n, pix);
             mx = fmaxf(mx, fabsf(v));
-            store_out<bf16>(a, v, img, oy, ox, n);
+            if (a.out_f16)
+              store_out<f16>(a, v, img, oy, ox, n);
+            else
+              store_out<bf16>(a, v, img, oy, ox, n);
           }
         }
       }
@@ -810,14 +821,18 @@ hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, int mr, hipStre
   if (e != hipSuccess || a.splits == 1) return e;
   if (!a.compact && !a.add && a.cout % 8 == 0) {
     const dim3 g(grid_1d((size_t)a.out_h * a.out_w * (a.cout / 8)), a.n);
-    if (a.bf16act)
+    if (a.bf16act && a.out_f16)
+      conv_reduce8_kernel<f16><<<g, 256, 0, s>>>(a);
+    else if (a.bf16act)
       conv_reduce8_kernel<bf16><<<g, 256, 0, s>>>(a);
     else
       conv_reduce8_kernel<float><<<g, 256, 0, s>>>(a);
     return hipGetLastError();
   }
   const dim3 g(grid_1d((size_t)a.out_h * a.out_w * a.cout), a.n);
-  if (a.bf16act)
+  if (a.bf16act && a.out_f16)
+    conv_reduce_kernel<f16><<<g, 256, 0, s>>>(a);
+  else if (a.bf16act)
     conv_reduce_kernel<bf16><<<g, 256, 0, s>>>(a);
   else
     conv_reduce_kernel<float><<<g, 256, 0, s>>>(a);

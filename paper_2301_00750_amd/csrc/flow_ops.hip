@@ -1,5 +1,7 @@
 // Bandwidth-bound steps of the flow network: frame staging, flow upsampling,
 // the fused feature warp + cost volume, and the final upsample-and-crop.
+#include <type_traits>
+
 #include "act.h"
 #include "tc_internal.h"
 
@@ -188,11 +190,17 @@ __device__ inline const T* vbase(const View& v, int img, size_t img_elems) {
                         : reinterpret_cast<const T*>(v.b) + (size_t)(img - v.nsplit) * img_elems;
 }
 
-template <int R, typename T>
+// T = storage type of the features (float, bfloat16 or float16), TZ = of Z.
+// Float16 features: the warped F2 tile is rounded to float16 in LDS (one
+// 16-byte word per position) and each displacement's 8-channel product is
+// four v_dot2_f32_f16 (float16 products, float32 sums).
+template <int R, typename T, typename TZ>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void warp_cv_kernel(CvArgs a) {
   constexpr int D = 2 * R + 1, NCV = D * D;
   constexpr int HY = CV_TY + 2 * R, HX = CV_TX + 2 * R, NPOS = HY * HX;
+  constexpr bool H = std::is_same<T, f16>::value;
   __shared__ f4 s2[2][NPOS];
+  u4* s2h = reinterpret_cast<u4*>(&s2[0][0]);  // float16 tile (H)
   __shared__ int2 s_tap[NPOS];     // (pixel index of the top-left tap, validity bits of the 4 taps)
   __shared__ float2 s_frac[NPOS];  // (ax, ay)
 
@@ -262,6 +270,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void w
                                             ((size_t)(valid ? y : 0) * w + (valid ? x : 0)) * 8));
     for (int p = tid; p < NPOS; p += 256) {
       const int2 tp = s_tap[p];
+      if constexpr (H) {
+        u4 word = u4{0u, 0u, 0u, 0u};
+        if (!U) {
+          if (tp.y) word = ldg(reinterpret_cast<const u4*>(f2c + (size_t)tp.x * 8));
+        } else {
+          const float2 fr = s_frac[p];
+          float acc8[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            if ((tp.y >> t) & 1) {
+              const float wt = ((t & 1) ? fr.x : 1.f - fr.x) * ((t >> 1) ? fr.y : 1.f - fr.y);
+              float v[8];
+              load8g(f2c + ((size_t)tp.x + (t & 1) + (t >> 1) * (size_t)w) * 8, v);
+#pragma unroll
+              for (int e = 0; e < 8; ++e) acc8[e] = fmaf(wt, v[e], acc8[e]);
+            }
+          }
+          word = u4{pack2h(acc8[0], acc8[1]), pack2h(acc8[2], acc8[3]),
+                    pack2h(acc8[4], acc8[5]), pack2h(acc8[6], acc8[7])};
+        }
+        s2h[p] = word;
+        continue;
+      }
       f4 lo = f4{0.f, 0.f, 0.f, 0.f}, hi = lo;
       if (!U) {
         if (sizeof(T) == 4 || tp.y) {
@@ -304,7 +335,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void w
       s2[1][p] = hi;
     }
     __syncthreads();
-    if (valid) {
+    if (H && valid) {
+      // (vector components are copied to plain arrays before the bit casts:
+      // hipcc's __builtin_bit_cast of an ext_vector component reads the
+      // vector's first component)
+      const unsigned aw[4] = {f1w.x, f1w.y, f1w.z, f1w.w};
+      h2 av[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) av[k] = __builtin_bit_cast(h2, aw[k]);
+#pragma unroll
+      for (int dy = 0; dy < D; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < D; ++dx) {
+          const u4 b = s2h[(ly + dy) * HX + lx + dx];
+          const unsigned bw[4] = {b.x, b.y, b.z, b.w};
+          float sacc = acc[dy * D + dx];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            sacc = __builtin_amdgcn_fdot2(av[k], __builtin_bit_cast(h2, bw[k]), sacc, false);
+          acc[dy * D + dx] = sacc;
+        }
+    } else if (valid) {
       float v1[8];
       if constexpr (sizeof(T) == 2) {
         const unsigned wd[4] = {f1w.x, f1w.y, f1w.z, f1w.w};
@@ -356,7 +407,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void w
       uy = u.y;
     }
     constexpr int ZCB = (NCV + 2 + 7) / 8;
-    T* z = reinterpret_cast<T*>(a.Z) + (size_t)img * ZCB * plane + ((size_t)y * w + x) * 8;
+    TZ* z = reinterpret_cast<TZ*>(a.Z) + (size_t)img * ZCB * plane + ((size_t)y * w + x) * 8;
 #pragma unroll
     for (int b = 0; b < ZCB; ++b) {
       float v[8];
@@ -521,10 +572,12 @@ hipError_t launch_warp_cost_volume(const CvArgs& a, hipStream_t s) {
   if (a.radius != 4 || a.C % 8 != 0 || a.zcb != (81 + 2 + 7) / 8) return hipErrorInvalidValue;
   if (a.splits < 1 || a.cps < 1 || (a.splits > 1 && !a.partial)) return hipErrorInvalidValue;
   dim3 grid(cdiv(a.w, CV_TX), cdiv(a.h, CV_TY), a.n * a.splits);
-  if (a.bf16act)
-    warp_cv_kernel<4, bf16><<<grid, 256, 0, s>>>(a);
+  if (a.bf16act && a.f16feat)
+    warp_cv_kernel<4, f16, bf16><<<grid, 256, 0, s>>>(a);
+  else if (a.bf16act)
+    warp_cv_kernel<4, bf16, bf16><<<grid, 256, 0, s>>>(a);
   else
-    warp_cv_kernel<4, float><<<grid, 256, 0, s>>>(a);
+    warp_cv_kernel<4, float, float><<<grid, 256, 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.splits == 1) return e;
   const dim3 g(grid_for((size_t)a.zcb * 8 * a.h * a.w), a.n);

@@ -90,6 +90,10 @@ struct ConvArgs {
   int splits, cps;
   float* partial;
   int bf16act;  // input and (blocked) output activations stored as bfloat16
+  // ... except: bit v of in_f16 set = view v (in0, in1) stored as float16
+  // (converted to bfloat16, or FP8, when staged); out_f16 = blocked output
+  // stored as float16
+  int in_f16, out_f16;
   int fp8;      // FP8 E4M3 MFMA: inputs scaled by max(ain) / 448, weights by wscale
   AmaxIn ain[3];
   const float* wscale;  // per output channel (np)
@@ -146,6 +150,9 @@ struct CvArgs {
   int splits, cps;
   float* partial;
   int bf16act;  // features and Z stored as bfloat16
+  int f16feat;  // with bf16act: features stored as float16, warped into float16
+                // and correlated with float16 products and float32 sums (Z stays
+                // bfloat16)
   unsigned* aout;  // per-image amax of the cost-volume outputs, or null
 };
 struct CvPlan {

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libtcflow.so")
 # static scratch of tc_flow_estimate_pair_noalloc (TC_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 256 << 20
 TC_FP32, TC_BF16, TC_FP8_E4M3 = 0, 1, 2
+TC_PREC_BF16_FEATURES = 0x100  # OR-ed into TC_BF16 / TC_FP8_E4M3: bfloat16 pyramid features
 
 EXPORTS = (
     "tc_status_str", "tc_version", "tc_weight_floats", "tc_net_create", "tc_net_destroy",

@@ -176,6 +176,22 @@ def flow_err(a, b):
     return e.mean(), e.max()
 
 
+_FULLHD = {}
+
+
+def fullhd_case():
+    """The 1920x1080 pair of the layered scene (seed 0) and the oracle's flow
+    pair on it, computed once per module."""
+    if not _FULLHD:
+        d = synth.load_desc("fullhd")
+        blob = synth.he_weights(d)
+        sc = synth.LayeredScene(1920, 1080, seed=0)
+        I0, I1 = sc.frame(0), sc.frame(1)
+        _FULLHD.update(d=d, blob=blob, I0=I0, I1=I1,
+                       ref=O.flow_pair(f64(I0), f64(I1), O.unpack_weights(blob, d), d))
+    return _FULLHD
+
+
 def sub_desc(d, levels):
     s = dict(d)
     s["levels"] = levels
@@ -274,16 +290,12 @@ def test_stream_state_sequence_vs_oracle(tc, tiny):
 
 
 def test_fullhd_pair_vs_oracle(tc):
-    d = synth.load_desc("fullhd")
-    blob = synth.he_weights(d)
-    wts = O.unpack_weights(blob, d)
-    net = tc.Net(d, blob)
-    sc = synth.LayeredScene(1920, 1080, seed=0)
-    I0, I1 = sc.frame(0), sc.frame(1)
+    c = fullhd_case()
+    net = tc.Net(c["d"], c["blob"])
     say("[flow] 1920x1080 pair")
-    fw, bw = net.flow_estimate_pair(g(I0[None]), g(I1[None]))
+    fw, bw = net.flow_estimate_pair(g(c["I0"][None]), g(c["I1"][None]))
     torch.cuda.synchronize()
-    rfw, rbw = O.flow_pair(f64(I0), f64(I1), wts, d)
+    rfw, rbw = c["ref"]
     for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
         mean, mx = flow_err(a, b)
         say(f"   {name}: EPE mean={mean:.3e} max={mx:.3e}")
@@ -376,19 +388,45 @@ def test_bf16_batch_invariance_and_determinism(tc, tiny):
     assert torch.equal(s1[0][0], fw[1]) and torch.equal(s1[1][0], bw[1])
 
 
-def test_bf16_fullhd_pair_vs_oracle(tc):
-    d = synth.load_desc("fullhd")
-    blob = synth.he_weights(d)
-    wts = O.unpack_weights(blob, d)
-    net = tc.Net(d, blob, precision=tc.TC_BF16)
-    sc = synth.LayeredScene(1920, 1080, seed=0)
-    I0, I1 = sc.frame(0), sc.frame(1)
-    say("[bf16 flow] 1920x1080 pair")
-    fw, bw = net.flow_estimate_pair(g(I0[None]), g(I1[None]))
+@pytest.mark.parametrize("features", ["f16", "bf16"])
+def test_bf16_fullhd_pair_vs_oracle(tc, features):
+    """BF16 form at 1080p; features = the storage of the pyramid features
+    (the cost volume's inputs): float16 with float16 products and float32
+    sums (the default), or bfloat16 correlated in float32."""
+    c = fullhd_case()
+    prec = tc.TC_BF16 | (tc.TC_PREC_BF16_FEATURES if features == "bf16" else 0)
+    net = tc.Net(c["d"], c["blob"], precision=prec)
+    say(f"[bf16 flow] 1920x1080 pair, {features} features")
+    fw, bw = net.flow_estimate_pair(g(c["I0"][None]), g(c["I1"][None]))
     torch.cuda.synchronize()
-    rfw, rbw = O.flow_pair(f64(I0), f64(I1), wts, d)
+    rfw, rbw = c["ref"]
     for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
         check_lowp(name, a, b)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_float16_features_tiny_vs_oracle(tc, prec):
+    """The float16 cost volume (the default of the BF16 and FP8 forms) and
+    the bfloat16-feature form against the oracle on the 128 x 96 pair, 4
+    levels: both within the guards, and float16 features (3 more mantissa
+    bits in the correlation's operands) no worse than bfloat16 ones beyond a
+    small margin."""
+    d = synth.load_desc("tiny")
+    blob = synth.he_weights(d)
+    wts = O.unpack_weights(blob, d)
+    base = tc.TC_BF16 if prec == "bf16" else tc.TC_FP8_E4M3
+    prev, cur, _, _ = synth.tiny_pair()
+    rfw, rbw = O.flow_pair(f64(prev), f64(cur), wts, d)
+    means = {}
+    for feat, flag in (("f16", 0), ("bf16", tc.TC_PREC_BF16_FEATURES)):
+        net = tc.Net(d, blob, precision=base | flag)
+        say(f"[{prec} flow] tiny, {feat} features")
+        fw, bw = net.flow_estimate_pair(g(prev[None]), g(cur[None]))
+        torch.cuda.synchronize()
+        for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
+            check_lowp(name, a, b)
+        means[feat] = max(flow_err(fw[0], rfw)[0], flow_err(bw[0], rbw)[0])
+    assert means["f16"] <= 1.5 * means["bf16"] + 1e-3
 
 
 # ---------------------------------------------------------------- the paper's consistency step
@@ -483,15 +521,11 @@ def test_fp8_batch_invariance_and_determinism(tc, tiny):
 
 
 def test_fp8_fullhd_pair_vs_oracle(tc):
-    d = synth.load_desc("fullhd")
-    blob = synth.he_weights(d)
-    wts = O.unpack_weights(blob, d)
-    net = tc.Net(d, blob, precision=tc.TC_FP8_E4M3)
-    sc = synth.LayeredScene(1920, 1080, seed=0)
-    I0, I1 = sc.frame(0), sc.frame(1)
+    c = fullhd_case()
+    net = tc.Net(c["d"], c["blob"], precision=tc.TC_FP8_E4M3)
     say("[fp8 flow] 1920x1080 pair")
-    fw, bw = net.flow_estimate_pair(g(I0[None]), g(I1[None]))
+    fw, bw = net.flow_estimate_pair(g(c["I0"][None]), g(c["I1"][None]))
     torch.cuda.synchronize()
-    rfw, rbw = O.flow_pair(f64(I0), f64(I1), wts, d)
+    rfw, rbw = c["ref"]
     for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
         check_lowp(name, a, b)
