@@ -42,7 +42,7 @@ ALPHAS = (0.0, 0.25, 0.5, 0.75, 1.0)
 # HBM bytes per launch of the level-1 conv1 at 1920x1080 (fw + bw), from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE scaled by a 1 GiB copy measured in the same runs (profiles/); valid only while the conv
 # source is the one they were measured on.
-CONV1_TRAFFIC = {"bytes": 1.1998e9, "source": "wino.hip", "sha256_16": "f721ea48355448da"}
+CONV1_TRAFFIC = {"bytes": None, "source": "wino4.hip", "sha256_16": None}
 METRIC = "1080p frames/s (flow+consistency) at stated EPE vs FP64 oracle; p99 frame ms"
 
 
@@ -68,17 +68,29 @@ def c1_flops(desc, h, w, level=1, images=2):
 
 
 def wino_layer(h_l, w_l, cout):
-    """Whether the library runs an FP32 stride-1 3x3 conv of this output
-    size by Winograd F(2x2, 3x3): output channels a multiple of 32 and at
-    least 32 tiles of 16 x 16 pixels per image."""
-    return cout % 32 == 0 and (-(-h_l // 16)) * (-(-w_l // 16)) >= 32
+    """Which Winograd form the library runs an FP32 stride-1 3x3 conv of this
+    output size with (output channels a multiple of 32): F(4x4, 3x3) from 128
+    regions of 16 x 32 pixels per image, else F(2x2, 3x3) from 32 tiles of
+    16 x 16 pixels; None for the direct kernel."""
+    if cout % 32:
+        return None
+    if (-(-h_l // 16)) * (-(-w_l // 32)) >= 128:
+        return "f4"
+    if (-(-h_l // 16)) * (-(-w_l // 16)) >= 32:
+        return "f2"
+    return None
 
 
-def wino_flops(direct_flops, h_l, w_l):
-    """MFMA FLOPs of a Winograd F(2x2, 3x3) conv: 16 products per 2x2 output
-    tile and channel pair instead of 36 (exact for even sizes, which every
-    level of a padded frame has)."""
-    return direct_flops * 16.0 / 36.0
+WINO_FRAC = {"f2": 16.0 / 36.0, "f4": 36.0 / 144.0}
+WINO_NAME = {"f2": "F(2x2,3x3)", "f4": "F(4x4,3x3)"}
+
+
+def wino_flops(direct_flops, form):
+    """MFMA FLOPs of a Winograd conv: F(2x2, 3x3) does 16 products per 2x2
+    output tile and channel pair instead of 36, F(4x4, 3x3) 36 per 4x4 tile
+    instead of 144 (exact when the sizes are multiples of the tile, as every
+    level of a 1080p frame is)."""
+    return direct_flops * WINO_FRAC[form]
 
 
 def refine_flops(desc, h, w, images=2):
@@ -115,8 +127,9 @@ def frame_lower_bound_ms(desc, h, w, peak_tflops, bpe=4, as_executed=False):
         hl, wl = hp >> l, wp >> l
         px = images * hl * wl
         f = 2.0 * px * 9 * cin * cout
-        if as_executed and bpe == 4 and wino_layer(hl, wl, cout):
-            f = wino_flops(f, hl, wl)
+        form = wino_layer(hl, wl, cout)
+        if as_executed and bpe == 4 and form:
+            f = wino_flops(f, form)
         return layer(px, cin, px, cout, f)
 
     # pyramid of one new frame
@@ -285,7 +298,7 @@ def main():
     m = 2 ** desc["levels"]
     h1, w1 = (-(-H // m) * m) >> 1, (-(-W // m) * m) >> 1
     c1_wino = wino_layer(h1, w1, desc["dec"][0])
-    c1_exec = wino_flops(c1_direct, h1, w1) if c1_wino else c1_direct
+    c1_exec = wino_flops(c1_direct, c1_wino) if c1_wino else c1_direct
     c1_tflops = c1_exec / (r["c1_ms"] * 1e-3) / 1e12
     t_star = frame_lower_bound_ms(desc, H, W, PEAK_FP32_MFMA)
     t_star_x = frame_lower_bound_ms(desc, H, W, PEAK_FP32_MFMA, as_executed=True)
@@ -326,10 +339,12 @@ def main():
             "t_star_as_executed_ms": round(t_star_x, 4),
             "frac_as_executed": round(t_star_x / r["ms"], 4),
             "note": "t_star: direct-convolution FLOPs (482 GFLOP per frame) at peak; "
-                    "as_executed: the Winograd layers at the 16/36 of those FLOPs they execute",
+                    "as_executed: the Winograd layers at the share of those FLOPs they execute "
+                    "(36/144 for F(4x4,3x3), 16/36 for F(2x2,3x3))",
         },
         "roofline": {
-            "kernel": ("conv3x3_f32_wino (level-1 decoder conv1 by Winograd F(2x2,3x3), fw+bw batch)"
+            "kernel": (f"conv3x3_f32_wino{'4' if c1_wino == 'f4' else ''} (level-1 decoder conv1 by "
+                       f"Winograd {WINO_NAME[c1_wino]}, fw+bw batch)"
                        if c1_wino else "conv3x3_f32_mfma (level-1 decoder conv1, fw+bw batch)"),
             "bound": "mfma",
             "achieved": round(c1_tflops, 2),
@@ -341,8 +356,9 @@ def main():
             "direct_equivalent_tflops": round(c1_direct / (r["c1_ms"] * 1e-3) / 1e12, 2),
             "avg_launch_ms": round(r["c1_ms"], 5),
             "launches": r["n_probe"],
-            "note": "achieved = the MFMA FLOPs the kernel executes (16/36 of direct convolution's "
-                    "for Winograd) per launch; direct_equivalent = direct convolution's FLOPs per "
+            "note": "achieved = the MFMA FLOPs the kernel executes (36/144 of direct convolution's "
+                    "for Winograd F(4x4,3x3), 16/36 for F(2x2,3x3)) per launch; direct_equivalent = "
+                    "direct convolution's FLOPs per "
                     "launch time; launches timed inside the throughput run, where two frames' "
                     "decoders share the GPU; alone_* = the same kernel in the latency pass",
             "alone_avg_launch_ms": round(r["c1_alone_ms"], 5),

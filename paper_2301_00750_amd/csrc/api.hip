@@ -34,6 +34,7 @@ namespace {
 
 constexpr int kMaxN = 4096, kMaxHW = 16384;
 constexpr int kHeadMaxIn = 128;  // 16 channel blocks of 8 (launch_head)
+constexpr long kWino4Regions = 128;  // F(4x4, 3x3) from this many 16 x 32 regions per image
 constexpr size_t kAlign = 256;
 
 #define TC_TRY_HIP(x)                        \
@@ -429,7 +430,14 @@ int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, in
     // FP32 stride-1 layers with >= 32 tiles of 16 x 16 output pixels per
     // image (a per-image rule, so the choice never depends on the batch):
     // Winograd F(2x2, 3x3) on the matrix cores, without split K
-    if (L.wu && (long)cdiv(out_h, 16) * cdiv(out_w, 16) >= 32 && wino_ok(a, stride, L.kc)) {
+    // F(4x4, 3x3) on layers with >= kWino4Regions regions of 16 x 32 output
+    // pixels per image (also a per-image rule)
+    if (L.wu4 && (long)cdiv(out_h, 16) * cdiv(out_w, 32) >= kWino4Regions &&
+        wino_ok(a, stride, L.kc)) {
+      a.splits = 1;
+      a.cps = a.nchunks;
+      e = launch_conv3x3_wino4(a, L.wu4, s);
+    } else if (L.wu && (long)cdiv(out_h, 16) * cdiv(out_w, 16) >= 32 && wino_ok(a, stride, L.kc)) {
       a.splits = 1;
       a.cps = a.nchunks;
       e = launch_conv3x3_wino(a, L.wu, s);
@@ -696,6 +704,7 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     std::vector<float> b;
     std::vector<float> sc;  // FP8 per-output-channel weight scales
     std::vector<float> wu;  // Winograd-transformed weights (FP32 stride-1 layers)
+    std::vector<float> wu4;  // the same for F(4x4, 3x3)
   };
   std::vector<Packed> packed;
   std::vector<ConvLayer*> slots;
@@ -730,7 +739,10 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
       pk.w.resize(wf.size() * 4);
       memcpy(pk.w.data(), wf.data(), pk.w.size());
       if (stride1 && !head && kc == 8 && cout % 32 == 0)
+      {
         pack_conv_wino(W, cout, cin, cin_pad, cmap, pk.wu);
+        pack_conv_wino4(W, cout, cin, cin_pad, cmap, pk.wu4);
+      }
     }
     cl.cin = cin;
     cl.cout = cout;
@@ -808,6 +820,8 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     total = align_up(total + (pk.b.size() + pk.sc.size()) * sizeof(float), kAlign);
     offs.push_back(total);
     total = align_up(total + pk.wu.size() * sizeof(float), kAlign);
+    offs.push_back(total);
+    total = align_up(total + pk.wu4.size() * sizeof(float), kAlign);
   }
   for (auto& sp : sep) {
     offs.push_back(total);
@@ -821,22 +835,25 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
   }
   std::vector<char> host(total, 0);
   for (size_t i = 0; i < packed.size(); ++i) {
-    memcpy(host.data() + offs[3 * i], packed[i].w.data(), packed[i].w.size());
-    memcpy(host.data() + offs[3 * i + 1], packed[i].b.data(), packed[i].b.size() * sizeof(float));
+    const size_t* o = &offs[4 * i];  // w, b (+ FP8 scales), wu, wu4
+    memcpy(host.data() + o[0], packed[i].w.data(), packed[i].w.size());
+    memcpy(host.data() + o[1], packed[i].b.data(), packed[i].b.size() * sizeof(float));
     if (!packed[i].sc.empty())
-      memcpy(host.data() + offs[3 * i + 1] + packed[i].b.size() * sizeof(float),
-             packed[i].sc.data(), packed[i].sc.size() * sizeof(float));
+      memcpy(host.data() + o[1] + packed[i].b.size() * sizeof(float), packed[i].sc.data(),
+             packed[i].sc.size() * sizeof(float));
     if (!packed[i].wu.empty())
-      memcpy(host.data() + offs[3 * i + 2], packed[i].wu.data(), packed[i].wu.size() * sizeof(float));
-    slots[i]->w = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[3 * i]);
-    slots[i]->b = reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[3 * i + 1]);
+      memcpy(host.data() + o[2], packed[i].wu.data(), packed[i].wu.size() * sizeof(float));
+    if (!packed[i].wu4.empty())
+      memcpy(host.data() + o[3], packed[i].wu4.data(), packed[i].wu4.size() * sizeof(float));
+    char* base = static_cast<char*>(net->dmem);
+    slots[i]->w = reinterpret_cast<float*>(base + o[0]);
+    slots[i]->b = reinterpret_cast<float*>(base + o[1]);
     if (slots[i]->fp8) slots[i]->ws = slots[i]->b + packed[i].b.size();
-    slots[i]->wu = packed[i].wu.empty()
-                       ? nullptr
-                       : reinterpret_cast<float*>(static_cast<char*>(net->dmem) + offs[3 * i + 2]);
+    slots[i]->wu = packed[i].wu.empty() ? nullptr : reinterpret_cast<float*>(base + o[2]);
+    slots[i]->wu4 = packed[i].wu4.empty() ? nullptr : reinterpret_cast<float*>(base + o[3]);
   }
   for (size_t j = 0; j < sep.size(); ++j) {
-    const size_t o0 = offs[3 * packed.size() + 2 * j], o1 = offs[3 * packed.size() + 2 * j + 1];
+    const size_t o0 = offs[4 * packed.size() + 2 * j], o1 = offs[4 * packed.size() + 2 * j + 1];
     memcpy(host.data() + o0, sep[j].pw.data(), sep[j].pw.size());
     memcpy(host.data() + o1, sep[j].rest.data(), sep[j].rest.size() * sizeof(float));
     SepLayer& sl = net->ref[j];

@@ -57,6 +57,7 @@ struct ConvLayer {
   int fp8;         // same order, FP8 E4M3 bytes, scaled per output channel by ws
   float* ws;       // device, np per-output-channel weight scales (FP8 layers)
   float* wu;       // device, Winograd-transformed weights (pack_conv_wino), or null
+  float* wu4;      // device, F(4x4, 3x3) transformed weights (pack_conv_wino4), or null
 };
 
 // Per-image absolute-maximum slots (float bits as unsigned) of an activation
@@ -114,6 +115,11 @@ hipError_t launch_conv3x3(const ConvArgs& a, int stride, int kc, int mr, hipStre
 // multiple of 32, no split K.
 bool wino_ok(const ConvArgs& a, int stride, int kc);
 hipError_t launch_conv3x3_wino(const ConvArgs& a, const float* wu, hipStream_t s);
+// The same layers by Winograd F(4x4, 3x3) (wino4.hip): 36 instead of 64
+// products per 4x4 outputs and channel pair.
+hipError_t launch_conv3x3_wino4(const ConvArgs& a, const float* wu4, hipStream_t s);
+void pack_conv_wino4(const float* W, int cout, int cin, int cin_pad, const std::vector<int>& cmap,
+                     std::vector<float>& out);
 // 3x3 conv with two output channels (the estimator head) on vector ALUs,
 // FP32 activations.
 hipError_t launch_head(const ConvArgs& a, hipStream_t s);
