@@ -24,11 +24,14 @@
 // and 32 output channels.  Wave w owns M block w / 2 (tile rows 2 (w/2) and
 // 2 (w/2) + 1: 16 tiles) and N block w % 2 (16 channels).  K runs over
 // chunks of 4 input channels (one MFMA K step): the 18 x 34 input halo of the
-// chunk and its transformed weights are staged in one of two LDS stage
-// buffers while the matrix cores consume the other (the next chunk is
-// prefetched into registers meanwhile).  Lane l = 16 g + m transforms the
-// 6x6 patch of tile m for channel g: its 36 values are exactly its A
-// operands (A[m][k = g]) for the 36 GEMMs, so V never touches LDS.  The
+// chunk is staged in one of two LDS stage buffers while the matrix cores
+// consume the other (the next chunk is prefetched into registers meanwhile).
+// Lane l = 16 g + m transforms the 6x6 patch of tile m for channel g: its 36
+// values are exactly its A operands (A[m][k = g]) for the 36 GEMMs, so V
+// never touches LDS.  Its 36 B operands (the transformed weights of input g
+// and output m of its N block) are 144 contiguous bytes in global memory,
+// read straight into registers at the top of the chunk: the two waves of an
+// N block share them through L1/L2, and LDS carries only the halo.  The
 // accumulators of a lane hold all 36 positions of its 4 tiles, so the output
 // transform runs in registers; results go through LDS to whole 32-byte
 // channel-block stores.
@@ -49,16 +52,16 @@ struct Q4 {
   static constexpr int THREADS = 128 * QM;
   static constexpr int QY = 8 * QM, QX = 32;           // output rows and columns
   static constexpr int QHY = QY + 2, QHX = QX + 2;     // input halo
-  static constexpr int QRP = 36;                       // LDS row pitch of a staged plane (floats)
+  // LDS row pitch of a staged plane (floats): 40, so the tiles of the two
+  // tile rows of an M block (4 halo rows apart: 160 floats = 32 mod 64)
+  // read disjoint banks
+  static constexpr int QRP = 40;
   static constexpr int QAP = QHY * QRP + 8;            // LDS plane pitch (= 16 mod 32)
   static constexpr int QNA = QHY * QHX;                // halo pixels, one float4 (4 channels) each
   static constexpr int QRA = (QNA + THREADS - 1) / THREADS;
-  static constexpr int QUF = 2 * 64 * 36;              // weights per chunk and 32-channel slice
-  static constexpr int QNB = QUF / 4;                  // float4
-  static constexpr int QRB = (QNB + THREADS - 1) / THREADS;
-  static constexpr int QSTAGE = 4 * QAP + QUF;         // floats per stage buffer
+  static constexpr int QSTAGE = 4 * QAP;               // floats per stage buffer (halo only)
 };
-constexpr int QUF = 2 * 64 * 36;
+constexpr int QUF = 2 * 64 * 36;  // transformed weights per chunk and 32-channel slice
 constexpr int QOP = 20;  // epilogue LDS pitch per pixel (16 channels + 4)
 
 __device__ inline const float* qview_base(const View& v, int img, size_t img_floats) {
@@ -96,7 +99,7 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
                                                                      int nsl, int gx, int gy, int total) {
   using C = Q4<QM>;
   constexpr int THREADS = C::THREADS, QY = C::QY, QX = C::QX, QHX = C::QHX, QRP = C::QRP,
-                QAP = C::QAP, QNA = C::QNA, QRA = C::QRA, QNB = C::QNB, QRB = C::QRB,
+                QAP = C::QAP, QNA = C::QNA, QRA = C::QRA,
                 QSTAGE = C::QSTAGE;
   // two stage buffers; after the K loop, 128 pixels x QOP per wave for the epilogue
   constexpr int SMEM = 2 * QSTAGE > 2 * QM * 128 * QOP ? 2 * QSTAGE : 2 * QM * 128 * QOP;
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
   // Prefetch of a chunk: unconditional loads (addresses clamped into the
   // image, the same for every chunk, so computed once); the zero padding is
   // applied when the values are stored into LDS.
-  f4 ra[QRA], rb[QRB];
+  f4 ra[QRA];
   int off[QRA];
   unsigned inb = 0;
 #pragma unroll
@@ -152,12 +155,6 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
     const float* src = qview_base(v, img, in_plane * v.cbt) + (size_t)cb * in_plane + (ch & 1) * 4;
 #pragma unroll
     for (int j = 0; j < QRA; ++j) ra[j] = ldg(reinterpret_cast<const f4*>(src + off[j]));
-    const f4* ws = reinterpret_cast<const f4*>(wslice + (size_t)ch * QUF);
-#pragma unroll
-    for (int j = 0; j < QRB; ++j) {
-      const int i = tid + j * THREADS;
-      rb[j] = i < QNB ? ldg(ws + i) : f4{0.f, 0.f, 0.f, 0.f};
-    }
   };
   auto stash = [&](float* st) {
 #pragma unroll
@@ -173,24 +170,25 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
         st[3 * QAP + lp] = val.w;
       }
     }
-#pragma unroll
-    for (int j = 0; j < QRB; ++j) {
-      const int i = tid + j * THREADS;
-      if (i < QNB) reinterpret_cast<f4*>(st + 4 * QAP)[i] = rb[j];
-    }
   };
 
   // this lane's tile (A row m = lm): tile row 2 mblk + lm / 8, column lm % 8;
   // its patch in channel plane lg
   const int aoff = lg * QAP + 4 * (2 * mblk + (lm >> 3)) * QRP + 4 * (lm & 7);
   // its 36 transformed weights (B[k = lg][n = lm] of every position)
-  const int uoff = 4 * QAP + (nb * 64 + lane) * 36;
+  const float* ulane = wslice + (size_t)(nb * 64 + lane) * 36;
 
   fetch(0);
   stash(smem);
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
     const float* st = smem + (ch & 1) * QSTAGE;
+    f4 uq[9];
+    {
+      const f4* up = reinterpret_cast<const f4*>(ulane + (size_t)ch * QUF);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) uq[k] = ldg(up + k);
+    }
     if (ch + 1 < nch) fetch(ch + 1);
     // the patch, then V = B^T d B (columns first, then rows)
     float d[6][6];
@@ -222,10 +220,9 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
 #pragma unroll
       for (int qq = 0; qq < 6; ++qq) v[6 * p + qq] = y[qq];
     }
-    const f4* su = reinterpret_cast<const f4*>(st + uoff);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-      const f4 u = su[k];
+      const f4 u = uq[k];
       acc[4 * k + 0] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[4 * k + 0], u.x, acc[4 * k + 0], 0, 0, 0);
       acc[4 * k + 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[4 * k + 1], u.y, acc[4 * k + 1], 0, 0, 0);
       acc[4 * k + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[4 * k + 2], u.z, acc[4 * k + 2], 0, 0, 0);
