@@ -13,6 +13,7 @@
  *     least the size the matching *_bytes query returns, 256-byte aligned.
  *     The library never allocates on a call path and never frees caller
  *     memory.  Outputs must not alias inputs (except where stated).
+ *   - Calls that can fail return a tc_status value (as int).
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is only
  *     enqueued; nothing synchronises the host.  Argument, shape and
  *     workspace errors are returned before anything is enqueued; a kernel
@@ -26,6 +27,8 @@
 #define TCFLOW_H
 
 #include <stddef.h>
+
+#include <hip/hip_runtime_api.h> /* hipStream_t */
 
 #ifdef __cplusplus
 extern "C" {
@@ -122,7 +125,7 @@ TC_API size_t tc_pyramid_bytes(const tc_net* net, int n, int h, int w);
  * up to a multiple of 2^L, then each level applies a stride-2 and a stride-1
  * 3x3 conv, each followed by LeakyReLU.  Writes into `pyr`. */
 TC_API int tc_pyramid(const tc_net* net, const float* frames, int n, int h, int w, void* pyr,
-                      size_t pyr_bytes, void* stream);
+                      size_t pyr_bytes, hipStream_t stream);
 
 /* ---- flow -------------------------------------------------------------- */
 
@@ -141,7 +144,7 @@ TC_API size_t tc_decoder_workspace_bytes(const tc_net* net, int n, int h, int w)
  * Paper, Sec. 3.2 and supplementary S1. */
 TC_API int tc_flow_from_pyramids(const tc_net* net, const void* pyr1, const void* pyr2, int n,
                                  int h, int w, float* flow12, float* flow21, void* ws,
-                                 size_t ws_bytes, void* stream);
+                                 size_t ws_bytes, hipStream_t stream);
 
 /* Continuous batching over streams: one decoder pass for n (<= 16) frame
  * pairs whose pyramids live in separate one-image buffers (tc_pyramid with
@@ -152,21 +155,32 @@ TC_API size_t tc_decoder_list_workspace_bytes(const tc_net* net, int n, int h, i
 TC_API int tc_flow_from_pyramid_list(const tc_net* net, const void* const* pyr_prev,
                                      const void* const* pyr_cur, int n, int h, int w,
                                      float* const* flow_fw, float* const* flow_bw, void* ws,
-                                     size_t ws_bytes, void* stream);
+                                     size_t ws_bytes, hipStream_t stream);
 
 /* Scratch bytes of tc_flow_estimate / tc_flow_estimate_pair (two pyramids
  * plus the decoder scratch). */
 TC_API size_t tc_flow_workspace_bytes(const tc_net* net, int n, int h, int w);
 
-/* flow_estimate(prev, cur) -> flow from prev to cur on prev's grid. */
+/* flow_estimate(prev, cur) -> flow from prev to cur on prev's grid, in
+ * pixels (paper Sec. 3.1: the input video I and the optical flow between
+ * consecutive frames that warps the previous output; Sec. 3.2: the flow
+ * network).  prev, cur: n x 3 x h x w; flow: n x 2 x h x w (caller-owned
+ * device memory); ws: at least tc_flow_workspace_bytes(net, n, h, w) bytes,
+ * 256-byte aligned.  Builds both pyramids, then the coarse-to-fine decoder
+ * as tc_flow_from_pyramids.  TC_ERR_INVALID_ARG for null pointers or
+ * n, h, w < 1; TC_ERR_WORKSPACE for a small or misaligned workspace. */
 TC_API int tc_flow_estimate(const tc_net* net, const float* prev, const float* cur, int n, int h,
-                            int w, float* flow, void* ws, size_t ws_bytes, void* stream);
+                            int w, float* flow, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* flow_fw = flow(prev -> cur), flow_bw = flow(cur -> prev), sharing both
- * pyramids and one batched decoder pass. */
+ * pyramids and one batched decoder pass: the two flows the consistency step
+ * needs (paper Sec. 3.1, Eq. 4 warps O_{t-1} with the flow from t to t-1;
+ * the forward-backward test of the mask compares both; Sec. 3.2 network).
+ * Arguments, workspace and errors as for tc_flow_estimate; flow_bw must
+ * not be NULL. */
 TC_API int tc_flow_estimate_pair(const tc_net* net, const float* prev, const float* cur, int n,
                                  int h, int w, float* flow_fw, float* flow_bw, void* ws,
-                                 size_t ws_bytes, void* stream);
+                                 size_t ws_bytes, hipStream_t stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
@@ -188,7 +202,7 @@ TC_API int tc_flow_estimate_pair(const tc_net* net, const float* prev, const flo
 #define TC_NOALLOC_SCRATCH_BYTES (256u << 20)
 TC_API int tc_flow_estimate_pair_noalloc(const tc_net* net, const float* prev, const float* cur,
                                          int n, int h, int w, float* flow_fw, float* flow_bw,
-                                         void* stream);
+                                         hipStream_t stream);
 
 /* Flow pair of the paper's fast preset (Sec. 4.1, implementation details:
  * optical flow computed on half-sized inputs).  Each frame is reduced to
@@ -205,7 +219,7 @@ TC_API int tc_flow_estimate_pair_noalloc(const tc_net* net, const float* prev, c
 TC_API size_t tc_flow_half_workspace_bytes(const tc_net* net, int n, int h, int w);
 TC_API int tc_flow_estimate_pair_half(const tc_net* net, const float* prev, const float* cur,
                                       int n, int h, int w, float* flow_fw, float* flow_bw,
-                                      void* ws, size_t ws_bytes, void* stream);
+                                      void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---- consistency step -------------------------------------------------- */
 
@@ -223,7 +237,7 @@ TC_API int tc_flow_estimate_pair_half(const tc_net* net, const float* prev, cons
  * is written when not NULL.  For t = 1 the caller sets O_1 = P_1. */
 TC_API int tc_consistency_step(const float* stylized, const float* prev_out, const float* flow_fw,
                                const float* flow_bw, float alpha, int n, int h, int w, float* out,
-                               unsigned char* mask_or_null, void* stream);
+                               unsigned char* mask_or_null, hipStream_t stream);
 
 /* ---- the paper's full consistency step ------------------------------------ */
 
@@ -270,7 +284,7 @@ TC_API int tc_consistency_paper(const float* I_prev, const float* I, const float
                                 const float* P_prev, const float* P, const float* P_next,
                                 const float* O_prev, const float* flow_t_prev,
                                 const float* flow_t_next, const tc_paper_params* params, int n,
-                                int h, int w, float* out, void* ws, size_t ws_bytes, void* stream);
+                                int h, int w, float* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---- measurement probe -------------------------------------------------- */
 
@@ -280,7 +294,7 @@ TC_API int tc_consistency_paper(const float* I_prev, const float* I, const float
  * |f_b + f~_f|^2 <= 0.01 (|f_b|^2 + |f~_f|^2) + 0.5).  Used to fall back from
  * a student network's flows to the teacher's when too few pixels agree. */
 TC_API int tc_flow_agreement(const float* flow_fw, const float* flow_bw, int n, int h, int w,
-                             unsigned* counts, void* stream);
+                             unsigned* counts, hipStream_t stream);
 
 /* ---- training of a student network on teacher flows --------------------
  *
@@ -319,13 +333,13 @@ TC_API void tc_trainer_destroy(tc_trainer* t);
  * The gradient stays in the trainer; the loss (one float) is written to
  * device memory `loss_out` if not NULL.  Asynchronous on `stream`. */
 TC_API int tc_trainer_grad(tc_trainer* t, const float* A, const float* B, const float* teacher,
-                           int n, float* loss_out, void* stream);
+                           int n, float* loss_out, hipStream_t stream);
 /* tc_trainer_grad followed by one AdamW step. */
 TC_API int tc_trainer_step(tc_trainer* t, const float* A, const float* B, const float* teacher,
-                           int n, float* loss_out, void* stream);
+                           int n, float* loss_out, hipStream_t stream);
 /* Copies weights (which = 0), gradient (1), first (2) or second moment (3),
  * n_floats values in blob layout, to `dst` (host or device). */
-TC_API int tc_trainer_copy(const tc_trainer* t, int which, float* dst, void* stream);
+TC_API int tc_trainer_copy(const tc_trainer* t, int which, float* dst, hipStream_t stream);
 /* Number of AdamW steps taken. */
 TC_API int tc_trainer_steps_done(const tc_trainer* t);
 

@@ -885,7 +885,7 @@ size_t tc_pyramid_bytes(const tc_net* net, int n, int h, int w) {
 }
 
 int tc_pyramid(const tc_net* net, const float* frames, int n, int h, int w, void* pyr,
-               size_t pyr_bytes, void* stream) {
+               size_t pyr_bytes, hipStream_t stream) {
   if (!net || !frames || !pyr || !shape_ok(n, h, w)) return TC_ERR_INVALID_ARG;
   if (!aligned(pyr) || pyr_bytes < tc_pyramid_bytes(net, n, h, w)) return TC_ERR_WORKSPACE;
   return run_pyramid(net, frames, n, h, w, static_cast<char*>(pyr), (hipStream_t)stream);
@@ -898,7 +898,7 @@ size_t tc_decoder_workspace_bytes(const tc_net* net, int n, int h, int w) {
 
 int tc_flow_from_pyramids(const tc_net* net, const void* pyr1, const void* pyr2, int n, int h,
                           int w, float* flow12, float* flow21, void* ws, size_t ws_bytes,
-                          void* stream) {
+                          hipStream_t stream) {
   if (!net || !pyr1 || !pyr2 || !flow12 || !ws || !shape_ok(n, h, w)) return TC_ERR_INVALID_ARG;
   if (!aligned(ws) || !aligned(pyr1) || !aligned(pyr2)) return TC_ERR_WORKSPACE;
   if (ws_bytes < dec_layout(net, flow21 ? 2 * n : n, h, w).total) return TC_ERR_WORKSPACE;
@@ -915,7 +915,7 @@ size_t tc_decoder_list_workspace_bytes(const tc_net* net, int n, int h, int w) {
 int tc_flow_from_pyramid_list(const tc_net* net, const void* const* pyr_prev,
                               const void* const* pyr_cur, int n, int h, int w,
                               float* const* flow_fw, float* const* flow_bw, void* ws,
-                              size_t ws_bytes, void* stream) {
+                              size_t ws_bytes, hipStream_t stream) {
   if (!net || !pyr_prev || !pyr_cur || !flow_fw || !flow_bw || !ws || !shape_ok(n, h, w))
     return TC_ERR_INVALID_ARG;
   if (n > kTabMax / 4) return TC_ERR_UNSUPPORTED;
@@ -966,7 +966,7 @@ size_t tc_flow_workspace_bytes(const tc_net* net, int n, int h, int w) {
 }
 
 static int flow_common(const tc_net* net, const float* prev, const float* cur, int n, int h, int w,
-                       float* f12, float* f21, void* ws, size_t ws_bytes, void* stream) {
+                       float* f12, float* f21, void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!net || !prev || !cur || !f12 || !ws || !shape_ok(n, h, w)) return TC_ERR_INVALID_ARG;
   if (!aligned(ws) || ws_bytes < tc_flow_workspace_bytes(net, n, h, w)) return TC_ERR_WORKSPACE;
   const size_t pb = pyr_layout(net, n, h, w).total;
@@ -980,13 +980,13 @@ static int flow_common(const tc_net* net, const float* prev, const float* cur, i
 }
 
 int tc_flow_estimate(const tc_net* net, const float* prev, const float* cur, int n, int h, int w,
-                     float* flow, void* ws, size_t ws_bytes, void* stream) {
+                     float* flow, void* ws, size_t ws_bytes, hipStream_t stream) {
   return flow_common(net, prev, cur, n, h, w, flow, nullptr, ws, ws_bytes, stream);
 }
 
 int tc_flow_estimate_pair(const tc_net* net, const float* prev, const float* cur, int n, int h,
                           int w, float* flow_fw, float* flow_bw, void* ws, size_t ws_bytes,
-                          void* stream) {
+                          hipStream_t stream) {
   if (!flow_bw) return TC_ERR_INVALID_ARG;
   return flow_common(net, prev, cur, n, h, w, flow_fw, flow_bw, ws, ws_bytes, stream);
 }
@@ -1031,7 +1031,7 @@ int scratch_for(hipStream_t s, void** out) {
 extern "C" {
 
 int tc_flow_estimate_pair_noalloc(const tc_net* net, const float* prev, const float* cur, int n,
-                                  int h, int w, float* flow_fw, float* flow_bw, void* stream) {
+                                  int h, int w, float* flow_fw, float* flow_bw, hipStream_t stream) {
   if (!net || !prev || !cur || !flow_fw || !flow_bw || !shape_ok(n, h, w))
     return TC_ERR_INVALID_ARG;
   const size_t need = tc_flow_workspace_bytes(net, n, h, w);
@@ -1052,7 +1052,7 @@ size_t tc_flow_half_workspace_bytes(const tc_net* net, int n, int h, int w) {
 
 int tc_flow_estimate_pair_half(const tc_net* net, const float* prev, const float* cur, int n,
                                int h, int w, float* flow_fw, float* flow_bw, void* ws,
-                               size_t ws_bytes, void* stream) {
+                               size_t ws_bytes, hipStream_t stream) {
   if (!net || !prev || !cur || !flow_fw || !flow_bw || !ws || !shape_ok(n, h, w))
     return TC_ERR_INVALID_ARG;
   if (!aligned(ws) || ws_bytes < tc_flow_half_workspace_bytes(net, n, h, w))
@@ -1079,7 +1079,7 @@ int tc_flow_estimate_pair_half(const tc_net* net, const float* prev, const float
 
 int tc_consistency_step(const float* stylized, const float* prev_out, const float* flow_fw,
                         const float* flow_bw, float alpha, int n, int h, int w, float* out,
-                        unsigned char* mask_or_null, void* stream) {
+                        unsigned char* mask_or_null, hipStream_t stream) {
   if (!stylized || !prev_out || !flow_fw || !flow_bw || !out) return TC_ERR_INVALID_ARG;
   if (!shape_ok(n, h, w)) return TC_ERR_INVALID_ARG;
   if (!(alpha >= 0.f && alpha <= 1.f)) return TC_ERR_INVALID_ARG;
@@ -1092,7 +1092,7 @@ int tc_consistency_step(const float* stylized, const float* prev_out, const floa
 }
 
 int tc_flow_agreement(const float* flow_fw, const float* flow_bw, int n, int h, int w,
-                      unsigned* counts, void* stream) {
+                      unsigned* counts, hipStream_t stream) {
   if (!flow_fw || !flow_bw || !counts || !shape_ok(n, h, w)) return TC_ERR_INVALID_ARG;
   return launch_agreement(flow_fw, flow_bw, n, h, w, counts, (hipStream_t)stream) == hipSuccess
              ? TC_OK
@@ -1139,7 +1139,7 @@ int tc_consistency_paper(const float* I_prev, const float* I, const float* I_nex
                          const float* P_prev, const float* P, const float* P_next,
                          const float* O_prev, const float* flow_t_prev, const float* flow_t_next,
                          const tc_paper_params* prm, int n, int h, int w, float* out, void* ws,
-                         size_t ws_bytes, void* stream) {
+                         size_t ws_bytes, hipStream_t stream) {
   if (!I_prev || !I || !I_next || !P_prev || !P || !P_next || !O_prev || !flow_t_prev ||
       !flow_t_next || !prm || !out || !ws || !shape_ok(n, h, w))
     return TC_ERR_INVALID_ARG;

@@ -1246,7 +1246,7 @@ int tc_trainer_create(const tc_net_desc* desc, const float* host_weights, size_t
 }
 
 int tc_trainer_grad(tc_trainer* t, const float* A, const float* B, const float* teacher, int n,
-                    float* loss_out, void* stream) {
+                    float* loss_out, hipStream_t stream) {
   if (!t || !A || !B || !teacher || n < 1 || n > t->max_n) return TC_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
   int st = pack_all(t, s);
@@ -1261,7 +1261,7 @@ int tc_trainer_grad(tc_trainer* t, const float* A, const float* B, const float* 
 }
 
 int tc_trainer_step(tc_trainer* t, const float* A, const float* B, const float* teacher, int n,
-                    float* loss_out, void* stream) {
+                    float* loss_out, hipStream_t stream) {
   int st = tc_trainer_grad(t, A, B, teacher, n, loss_out, stream);
   if (st) return st;
   t->step += 1;
@@ -1273,7 +1273,7 @@ int tc_trainer_step(tc_trainer* t, const float* A, const float* B, const float* 
   return hipGetLastError() == hipSuccess ? TC_OK : TC_ERR_HIP;
 }
 
-int tc_trainer_copy(const tc_trainer* t, int which, float* dst, void* stream) {
+int tc_trainer_copy(const tc_trainer* t, int which, float* dst, hipStream_t stream) {
   if (!t || !dst || which < 0 || which > 3) return TC_ERR_INVALID_ARG;
   const float* src = which == 0 ? t->P : which == 1 ? t->G : which == 2 ? t->M : t->V;
   return hipMemcpyAsync(dst, src, t->nfl * 4, hipMemcpyDefault, (hipStream_t)stream) == hipSuccess
