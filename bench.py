@@ -109,6 +109,23 @@ def refine_flops(desc, h, w, images=2):
     return fl
 
 
+def refine_bytes(desc, h, w, bpe, images=2):
+    """HBM bytes of the refinement layers of one decoder pass (fw + bw): per
+    layer its input read once and its output written once, at the finest
+    estimator level (the depthwise result stays on chip)."""
+    ref = desc.get("refine") or {}
+    if not ref.get("ch"):
+        return 0.0
+    m = 2 ** desc["levels"]
+    f = desc.get("finest", 1)
+    px = images * ((-(-h // m) * m) >> f) * ((-(-w // m) * m) >> f)
+    cin, b = desc["dec"][1] + desc["dec"][2] + 2, 0.0
+    for co in ref["ch"]:
+        b += px * (cin + co) * (4 if co == 2 else bpe)  # the flow output is float
+        cin = co
+    return b
+
+
 def frame_lower_bound_ms(desc, h, w, peak_tflops, bpe=4, as_executed=False):
     """Sum over the unfused layer graph of max(FLOP / peak, bytes / HBM),
     bytes = each layer's input read once + output written once.  FLOPs are
@@ -462,13 +479,23 @@ def variant_leg(tcflow, vdesc, I, P, K, W, frames, forms, base_fps):
              "frame_roofline": {"t_star_ms": round(t_star, 4), "frac": round(t_star / rv["ms"], 4)}}
         if has_ref:
             rf = refine_flops(vdesc, H, W_)
+            rb = refine_bytes(vdesc, H, W_, 4 if form == "fp32" else 2)
             ach = rf / (rv["c1_alone_ms"] * 1e-3) / 1e12
+            floor_ms = max(rb / (PEAK_HBM * 1e9), rf / (mpeak * 1e12)) * 1e3
             e["refinement"] = {"kernel": "sepconv_mfma (all layers, fw+bw batch)",
                                "gflop_per_pass": round(rf / 1e9, 3),
+                               "hbm_mb_per_pass": round(rb / 1e6, 1),
+                               "flop_per_byte": round(rf / rb, 1),
+                               "bound": "hbm" if rb / (PEAK_HBM * 1e9) > rf / (mpeak * 1e12) else "mfma",
+                               "floor_ms": round(floor_ms, 5),
                                "avg_ms": round(rv["c1_ms"], 5),
                                "alone_avg_ms": round(rv["c1_alone_ms"], 5),
+                               "alone_frac_of_floor": round(floor_ms / rv["c1_alone_ms"], 4),
                                "alone_achieved_tflops": round(ach, 2), "peak_tflops": mpeak,
-                               "alone_frac": round(ach / mpeak, 4)}
+                               "alone_achieved_GBps": round(rb / (rv["c1_alone_ms"] * 1e-3) / 1e9, 1),
+                               "note": "floor = max(bytes / 8 TB/s, FLOPs / matrix peak) over the "
+                                       "layers' input and output activations; the depthwise "
+                                       "results never reach memory"}
         report[form] = e
     return {"report": report, "nets": nets, "desc": vdesc}
 
@@ -497,9 +524,9 @@ def student_leg(tcflow, nets, I, P, K, W, frames, base_fps):
     d1080 = dict(sd, height=H, width=W_)
     log(f"student bf16 1080p: timing {K} steps")
     rs = measure(tcflow, d1080, wts, tcflow.TC_BF16, I, P, K, W, frames)
-    out["bf16_1080p"] = {"value": round(rs["fps"], 2), "unit": "frames/s",
-                         "speedup_vs_teacher_fp32": round(rs["fps"] / base_fps, 3),
-                         "p99_frame_ms": round(float(np.percentile(rs["lat"], 99)), 4)}
+    unguarded = {"value": round(rs["fps"], 2), "unit": "frames/s",
+                 "speedup_vs_teacher_fp32": round(rs["fps"] / base_fps, 3),
+                 "p99_frame_ms": round(float(np.percentile(rs["lat"], 99)), 4)}
     s_bf16 = rs["net"]
     s_fp32 = tcflow.Net(sd, wts)
     s_init = tcflow.Net(sd, synth.he_weights(sd))  # the same network before training
@@ -549,10 +576,23 @@ def student_leg(tcflow, nets, I, P, K, W, frames, base_fps):
         prev_out = tcflow.consistency_step(P[t], prev_out, f, b, 0.5)
     ev1.record()
     torch.cuda.synchronize()
-    out["bf16_1080p_with_fallback_check"] = {
-        "value": round(n_chk / (ev0.elapsed_time(ev1) * 1e-3), 2), "unit": "frames/s",
-        "note": "one frame at a time: student pair, agreement count read by the host, teacher "
-                "pair when below the threshold, consistency step"}
+    guarded_fps = n_chk / (ev0.elapsed_time(ev1) * 1e-3)
+    s_epe = float(np.mean(epe_s))
+    # the student form's result: student flows guarded by the teacher fallback
+    out["bf16_1080p"] = {
+        "value": round(guarded_fps, 2), "unit": "frames/s",
+        "speedup_vs_teacher_fp32": round(guarded_fps / base_fps, 3),
+        "epe_vs_teacher_px": round(float(np.mean(epe_out)), 4),
+        "fallback_rate": round(fb.fallbacks / max(1, fb.frames), 4),
+        "note": "the student form as served: one frame at a time, student pair, agreement count "
+                "read by the host, the teacher's (BF16) pair when fewer than 90% of pixels agree, "
+                "consistency step"}
+    unguarded["epe_vs_teacher_px"] = round(s_epe, 4)
+    unguarded["within_0.25px_bar"] = bool(s_epe <= 0.25)
+    unguarded["note"] = ("the student's flows alone, no agreement check, throughput streaming; "
+                         f"EPE vs the FP32 teacher {s_epe:.2f} px" +
+                         (" (outside the 0.25 px bar)" if s_epe > 0.25 else ""))
+    out["bf16_1080p_unguarded"] = unguarded
     # 3840x2160: student vs teacher, BF16 streaming
     log("student 4K: generating frames")
     sc4 = synth.LayeredScene(3840, 2160, seed=7)
