@@ -273,6 +273,8 @@ def main():
     ap.add_argument("--variants", default="fullhd_sepref",
                     help="comma-separated network variants (configs) measured in every precision "
                          "form after the base network ('' = none)")
+    ap.add_argument("--graphs", type=int, default=1,
+                    help="time each form's unpipelined step eager and replayed as a HIP graph")
     ap.add_argument("--student", type=int, default=1,
                     help="measure the distilled student (weights/student.npy) at 1080p and 4K")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -410,6 +412,10 @@ def main():
     if forms:
         result["precision_forms"] = forms
 
+    if args.graphs:
+        log("hip graphs: eager vs graph per frame")
+        result["graph_step"] = graph_leg(tcflow, desc, blob, nets, I, P, args.frames)
+
     variants = {}
     for vname in [v for v in args.variants.split(",") if v]:
         vd = synth.load_desc(vname)
@@ -450,6 +456,57 @@ def main():
             for form, e in vepe.items():
                 result["variants"][vname][form]["epe_vs_oracle"] = e
     print(json.dumps(result), flush=True)
+
+
+def graph_leg(tcflow, desc, blob, nets, I, P, frames, n=60):
+    """Each precision form's streaming step, unpipelined, eager against
+    replayed as one HIP graph per frame (GraphStreamState: the frame and the
+    stylized frame copied into fixed input buffers, then one graph launch):
+    per-frame latency one frame at a time, and back-to-back throughput."""
+    H, W_ = desc["height"], desc["width"]
+    res = {}
+    for form, net in nets.items():
+        out = {}
+        for mode in ("eager", "graph"):
+            if mode == "eager":
+                st = tcflow.StreamState(net, 1, H, W_, device=I[0].device, pipelined=False)
+            else:
+                st = tcflow.GraphStreamState(net, 1, H, W_, device=I[0].device)
+            t = 0
+
+            def push(events=None):
+                nonlocal t
+                f = frame_index(t, frames)
+                st.push(I[f], P[f], ALPHAS[t % len(ALPHAS)], events=events)
+                t += 1
+
+            for _ in range(2 + 2 * len(ALPHAS)):  # every (parity, alpha) graph captured
+                push()
+            torch.cuda.synchronize()
+            lat = []
+            for _ in range(min(40, n)):
+                ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                push(ev)
+                torch.cuda.synchronize()
+                lat.append(ev[0].elapsed_time(ev[1]))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n):
+                push()
+            torch.cuda.synchronize()
+            fps = n / (time.perf_counter() - t0)
+            out[mode] = {"frames_per_s": round(fps, 2),
+                         "p50_frame_ms": round(float(np.percentile(lat, 50)), 4),
+                         "p99_frame_ms": round(float(np.percentile(lat, 99)), 4)}
+            if mode == "graph":
+                out[mode]["graphs"] = len(st.graphs)
+            del st
+        res[form] = out
+    res["note"] = ("unpipelined driver, one frame's work per step; graph = the step replayed as one "
+                   "HIP graph after copying the frame and the stylized frame into fixed input "
+                   "buffers (the copies are timed); latency = one frame at a time, its first "
+                   "operation to O_t")
+    return res
 
 
 def variant_leg(tcflow, vdesc, I, P, K, W, frames, forms, base_fps):

@@ -580,6 +580,56 @@ class StreamState:
         return self.fw[lane], self.bw[lane]
 
 
+class GraphStreamState:
+    """The unpipelined streaming driver with each frame's work (pyramid of
+    I_t, the flow pair from the two pyramids, the consistency step) replayed
+    as one HIP graph: captured once per buffer parity and strength alpha, then
+    launched with a single call.  The frame and the stylized frame are first
+    copied into fixed input buffers (where an upload would land), since a
+    graph's kernels read fixed addresses.  Frames 0 and 1 run eagerly (the
+    first frame only copies P; the second is the first decode, which runs
+    every kernel once before any capture).  Outputs are bitwise those of
+    StreamState."""
+
+    def __init__(self, net: Net, n: int, h: int, w: int, device="cuda"):
+        self.st = StreamState(net, n, h, w, device=device, pipelined=False)
+        self.I_in = torch.empty(n, 3, h, w, device=device)
+        self.P_in = torch.empty(n, 3, h, w, device=device)
+        self.graphs = {}
+
+    @property
+    def t(self):
+        return self.st.t
+
+    def push(self, I, P, alpha, events=None):
+        """Enqueue frame t on the current stream; returns O_t (a view into the
+        driver's double buffer).  ``events`` = (start, end) recorded around
+        the input copies and the frame's work."""
+        main = torch.cuda.current_stream()
+        if events:
+            events[0].record(main)
+        self.I_in.copy_(I)
+        self.P_in.copy_(P)
+        t = self.st.t
+        if t < 2:
+            out = self.st.push(self.I_in, self.P_in, alpha)
+        else:
+            key = (t % 2, float(alpha))
+            g = self.graphs.get(key)
+            if g is None:
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    self.st.push(self.I_in, self.P_in, alpha)
+                self.st.t = t  # capture records the frame's work; it runs at replay
+                self.graphs[key] = g
+            g.replay()
+            self.st.t = t + 1
+            out = self.st.out[t % 2]
+        if events:
+            events[1].record(main)
+        return out
+
+
 def train_params(**kw):
     """tc_train_default_params with fields overridden by keyword."""
     p = TrainParams()
