@@ -318,6 +318,32 @@ void pack_conv_fp8(const float* W, const float* b, int cout, int cin, int cin_pa
   for (int o = 0; o < cout; ++o) bout[o] = b[o];
 }
 
+// FP8 packing for conv3x3_f8k128: per K step of 16 (tap, block) pairs
+// (tap-major, k = tap * nblk + block, zero past the last pair), per lane
+// group g and output channel n, the 8 channels of pairs 16 step + 4 g + j
+// (j = 0..3), each output channel scaled by scale[o] (as pack_conv_fp8).
+void pack_conv_f8k128(const float* W, int cout, int cin, int cin_pad, const std::vector<int>& cmap,
+                      const std::vector<float>& scale, int np, std::vector<uint8_t>& wout,
+                      int& nsteps) {
+  const int nblk = cin_pad / 8, npairs = 9 * nblk;
+  nsteps = f8k128_steps(cin_pad);
+  wout.assign((size_t)nsteps * 4 * np * 32, 0);
+  for (int s = 0; s < nsteps; ++s)
+    for (int g = 0; g < 4; ++g)
+      for (int j = 0; j < 4; ++j) {
+        const int k = 16 * s + 4 * g + j;
+        if (k >= npairs) continue;
+        const int tap = k / nblk, blk = k % nblk;
+        for (int o = 0; o < cout; ++o)
+          for (int c = 0; c < 8; ++c) {
+            const int src = cmap[blk * 8 + c];
+            if (src < 0) continue;
+            wout[(((size_t)s * 4 + g) * np + o) * 32 + j * 8 + c] =
+                host_f2e4m3(W[((size_t)o * cin + src) * 9 + tap] / scale[o]);
+          }
+      }
+}
+
 // Refinement layer packing.  Pointwise weights: per K chunk (16 channels for
 // FP32, 32 for BF16), per 16-channel output block and lane l, the K/4 values
 // W[16 nb + l % 16][K c + (K/4) (l / 16) + e] (float, or bfloat16), i.e. one
@@ -441,6 +467,9 @@ int conv_layer(const ConvLayer& L, const View& in0, int nb0, const View& in1, in
       a.splits = 1;
       a.cps = a.nchunks;
       e = launch_conv3x3_wino(a, L.wu, s);
+    } else if (L.w8 && f8k128_ok(a, stride, p.mr, L.nsteps8)) {
+      // FP8 on the K = 128 matrix instruction (layers without split K)
+      e = launch_conv3x3_f8k128(a, L.w8, L.nsteps8, p.mr, s);
     } else
       e = launch_conv3x3(a, stride, L.kc, p.mr, s);
   }
@@ -705,6 +734,8 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     std::vector<float> sc;  // FP8 per-output-channel weight scales
     std::vector<float> wu;  // Winograd-transformed weights (FP32 stride-1 layers)
     std::vector<float> wu4;  // the same for F(4x4, 3x3)
+    std::vector<uint8_t> w8;  // FP8 layers: the K = 128 MFMA packing
+    int nsteps8 = 0;
   };
   std::vector<Packed> packed;
   std::vector<ConvLayer*> slots;
@@ -728,6 +759,7 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
       pack_conv_fp8(W, b, cout, cin, cin_pad, cmap, wq, pk.b, pk.sc, np);
       pk.w.resize(wq.size());
       memcpy(pk.w.data(), wq.data(), pk.w.size());
+      if (stride1) pack_conv_f8k128(W, cout, cin, cin_pad, cmap, pk.sc, np, pk.w8, pk.nsteps8);
     } else if (cl.bf16) {
       std::vector<uint16_t> wb;
       pack_conv_bf16(W, b, cout, cin, cin_pad, cmap, wb, pk.b, np);
@@ -822,6 +854,8 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
     total = align_up(total + pk.wu.size() * sizeof(float), kAlign);
     offs.push_back(total);
     total = align_up(total + pk.wu4.size() * sizeof(float), kAlign);
+    offs.push_back(total);
+    total = align_up(total + pk.w8.size(), kAlign);
   }
   for (auto& sp : sep) {
     offs.push_back(total);
@@ -835,7 +869,7 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
   }
   std::vector<char> host(total, 0);
   for (size_t i = 0; i < packed.size(); ++i) {
-    const size_t* o = &offs[4 * i];  // w, b (+ FP8 scales), wu, wu4
+    const size_t* o = &offs[5 * i];  // w, b (+ FP8 scales), wu, wu4, w8
     memcpy(host.data() + o[0], packed[i].w.data(), packed[i].w.size());
     memcpy(host.data() + o[1], packed[i].b.data(), packed[i].b.size() * sizeof(float));
     if (!packed[i].sc.empty())
@@ -845,15 +879,18 @@ int tc_net_create(const tc_net_desc* desc, const float* host_weights, size_t n_f
       memcpy(host.data() + o[2], packed[i].wu.data(), packed[i].wu.size() * sizeof(float));
     if (!packed[i].wu4.empty())
       memcpy(host.data() + o[3], packed[i].wu4.data(), packed[i].wu4.size() * sizeof(float));
+    if (!packed[i].w8.empty()) memcpy(host.data() + o[4], packed[i].w8.data(), packed[i].w8.size());
     char* base = static_cast<char*>(net->dmem);
     slots[i]->w = reinterpret_cast<float*>(base + o[0]);
     slots[i]->b = reinterpret_cast<float*>(base + o[1]);
     if (slots[i]->fp8) slots[i]->ws = slots[i]->b + packed[i].b.size();
     slots[i]->wu = packed[i].wu.empty() ? nullptr : reinterpret_cast<float*>(base + o[2]);
     slots[i]->wu4 = packed[i].wu4.empty() ? nullptr : reinterpret_cast<float*>(base + o[3]);
+    slots[i]->w8 = packed[i].w8.empty() ? nullptr : static_cast<void*>(base + o[4]);
+    slots[i]->nsteps8 = packed[i].nsteps8;
   }
   for (size_t j = 0; j < sep.size(); ++j) {
-    const size_t o0 = offs[4 * packed.size() + 2 * j], o1 = offs[4 * packed.size() + 2 * j + 1];
+    const size_t o0 = offs[5 * packed.size() + 2 * j], o1 = offs[5 * packed.size() + 2 * j + 1];
     memcpy(host.data() + o0, sep[j].pw.data(), sep[j].pw.size());
     memcpy(host.data() + o1, sep[j].rest.data(), sep[j].rest.size() * sizeof(float));
     SepLayer& sl = net->ref[j];

@@ -58,6 +58,8 @@ struct ConvLayer {
   float* ws;       // device, np per-output-channel weight scales (FP8 layers)
   float* wu;       // device, Winograd-transformed weights (pack_conv_wino), or null
   float* wu4;      // device, F(4x4, 3x3) transformed weights (pack_conv_wino4), or null
+  void* w8;        // device, FP8 weights for conv3x3_f8k128 (pack_conv_f8k128), or null
+  int nsteps8;     // its K steps of 16 (tap, block) pairs
 };
 
 // Per-image absolute-maximum slots (float bits as unsigned) of an activation
@@ -120,6 +122,14 @@ hipError_t launch_conv3x3_wino(const ConvArgs& a, const float* wu, hipStream_t s
 hipError_t launch_conv3x3_wino4(const ConvArgs& a, const float* wu4, hipStream_t s);
 void pack_conv_wino4(const float* W, int cout, int cin, int cin_pad, const std::vector<int>& cmap,
                      std::vector<float>& out);
+// FP8 E4M3 3x3 conv on the K = 128 FP8 MFMA (conv_f8.hip): stride 1, no
+// split K, blocked outputs; the weights packed by pack_conv_f8k128 as
+// [step][lane group (4)][n (np)][4 pairs x 8 channels] bytes, pair k = 16 step
+// + 4 group + j taken tap-major (k = tap * nblk + block).
+int f8k128_steps(int cin_pad);
+bool f8k128_ok(const ConvArgs& a, int stride, int mr, int nsteps);
+hipError_t launch_conv3x3_f8k128(const ConvArgs& a, const void* w8, int nsteps, int mr,
+                                 hipStream_t s);
 // 3x3 conv with two output channels (the estimator head) on vector ALUs,
 // FP32 activations.
 hipError_t launch_head(const ConvArgs& a, hipStream_t s);

@@ -520,6 +520,34 @@ def test_fp8_batch_invariance_and_determinism(tc, tiny):
     assert torch.equal(s1[0][0], fw[1]) and torch.equal(s1[1][0], bw[1])
 
 
+def test_fp8_k128_ragged_and_batch_vs_oracle(tc):
+    """FP8 form at 1040 x 1680 (4-level net): the estimators of levels 1
+    (520 x 840) and 2 (260 x 420) run on the K = 128 FP8 matrix instruction,
+    with tiles cut by the image edge on both axes.  Against the oracle at
+    the precision forms' bars, and a batch of two pairs equal to each pair
+    alone, bitwise."""
+    d = synth.load_desc("tiny")
+    blob = synth.he_weights(d)
+    wts = O.unpack_weights(blob, d)
+    net = tc.Net(d, blob, precision=tc.TC_FP8_E4M3)
+    sc = synth.LayeredScene(1680, 1040, seed=3)
+    I0, I1 = sc.frame(0), sc.frame(1)
+    say("[fp8 flow] 1040x1680 pair, 4 levels (K = 128 FP8 levels 1-2)")
+    fw, bw = net.flow_estimate_pair(g(I0[None]), g(I1[None]))
+    torch.cuda.synchronize()
+    rfw, rbw = O.flow_pair(f64(I0), f64(I1), wts, d)
+    for name, a, b in (("fw", fw[0], rfw), ("bw", bw[0], rbw)):
+        check_lowp(name, a, b)
+    sc2 = synth.LayeredScene(1680, 1040, seed=4)
+    A = torch.stack([I0, sc2.frame(0)])
+    B = torch.stack([I1, sc2.frame(1)])
+    fw2, bw2 = net.flow_estimate_pair(g(A), g(B))
+    s1 = net.flow_estimate_pair(g(A[1:]), g(B[1:]))
+    torch.cuda.synchronize()
+    assert torch.equal(fw2[0], fw[0]) and torch.equal(bw2[0], bw[0])
+    assert torch.equal(s1[0][0], fw2[1]) and torch.equal(s1[1][0], bw2[1])
+
+
 def test_fp8_fullhd_pair_vs_oracle(tc):
     c = fullhd_case()
     net = tc.Net(c["d"], c["blob"], precision=tc.TC_FP8_E4M3)
