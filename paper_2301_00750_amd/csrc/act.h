@@ -136,6 +136,18 @@ __device__ inline u2v pack8_fp8(const float (&v)[8], float inv_scale) {
   return u2v{(unsigned)lo, (unsigned)hi};
 }
 
+// 8 floats -> 8 FP8 E4M3 after multiplying by `inv_scale`, without clamping:
+// for callers whose |v| * inv_scale is at most 448 by construction (an
+// input scale derived from a bound of |v|, with margin for the rounding of
+// the stored values).
+__device__ inline u2v pack8_fp8_nosat(const float (&v)[8], float inv_scale) {
+  int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0] * inv_scale, v[1] * inv_scale, 0, false);
+  lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[2] * inv_scale, v[3] * inv_scale, lo, true);
+  int hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[4] * inv_scale, v[5] * inv_scale, 0, false);
+  hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[6] * inv_scale, v[7] * inv_scale, hi, true);
+  return u2v{(unsigned)lo, (unsigned)hi};
+}
+
 // Each image's absolute maximum is spread over kAmaxSub sub-slots, each on
 // its own 128-byte line, so that the workgroups of a kernel do not all hit
 // one address; a consumer takes the maximum of the sub-slots.

@@ -664,24 +664,47 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
     // store per value.  The staging buffers are free after the K loop.
     bf16* so = reinterpret_cast<bf16*>(sB) + (size_t)wave * (TW * NP);
     const size_t plane = (size_t)a.out_h * a.out_w;
+    // LeakyReLU as max(v, slope v) (0 <= slope <= 1; slope 1 = none); the
+    // amax only when a consumer needs it; the storage type chosen once
+    const float slope = a.lrelu ? a.slope : 1.f;
+    const bool track = a.aout != nullptr;
+    float osc[NB], bn[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int n = nb * 16 + lm;
+      osc[nb] = F8 ? sa * a.wscale[n] : 1.f;
+      bn[nb] = n < a.cout ? a.b[n] : 0.f;
+    }
 #pragma unroll
     for (int mb = 0; mb < MR; ++mb) {
       const int oy = ty0 + wave * MR + mb;
       __syncthreads();
+      float y[NB][4];
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int n = nb * 16 + lm;
-        const bool nok = n < a.cout;
-        const float osc = F8 ? sa * a.wscale[n] : 1.f;
-        const float bn = nok ? a.b[n] : 0.f;
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int vv = 0; vv < 4; ++vv) {
-          const int px = 4 * lk + vv;
-          float v = acc[mb][nb][vv] * osc + bn;
-          if (a.lrelu) v = v >= 0.f ? v : a.slope * v;
-          if (nok && oy < a.out_h && tx0 + px < a.out_w) mx = fmaxf(mx, fabsf(v));
-          so[px * NP + n] = a.out_f16 ? __builtin_bit_cast(bf16, (f16)v) : f2bf(v);
+          const float v = F8 ? fmaf(acc[mb][nb][vv], osc[nb], bn[nb]) : acc[mb][nb][vv] + bn[nb];
+          y[nb][vv] = fmaxf(v, slope * v);
         }
+      if (track && oy < a.out_h) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv)
+            if (nb * 16 + lm < a.cout && tx0 + 4 * lk + vv < a.out_w) mx = fmaxf(mx, fabsf(y[nb][vv]));
+      }
+      if (a.out_f16) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv)
+            so[(4 * lk + vv) * NP + nb * 16 + lm] = __builtin_bit_cast(bf16, (f16)y[nb][vv]);
+      } else {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv) so[(4 * lk + vv) * NP + nb * 16 + lm] = f2bf(y[nb][vv]);
       }
       __syncthreads();
       if (oy < a.out_h) {

@@ -83,12 +83,17 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f8k128(ConvArgs a, const unsig
   const int iy0 = ty0 * S - 1, ix0 = tx0 * S - 1;
   const size_t in_plane = (size_t)a.in_h * a.in_w * 8;
 
+  // Input scale: the stored inputs are the producers' values rounded to
+  // bfloat16 or float16, at most 2^-8 above the recorded maximum m in
+  // magnitude, so x * 448 / (m (1 + 2^-7)) stays within 448 and the FP8
+  // conversion needs no clamp.
   float sa = 1.f, inv_sa = 1.f;
   {
     const float m = fmaxf(f8_amax_of(a.ain[0], img), fmaxf(f8_amax_of(a.ain[1], img), f8_amax_of(a.ain[2], img)));
     if (m > 0.f && m < 3.0e38f) {
-      sa = m / kFp8Max;
-      inv_sa = kFp8Max / m;
+      const float mm = m * (1.f + 0.0078125f);
+      sa = mm / kFp8Max;
+      inv_sa = kFp8Max / mm;
     }
   }
 
@@ -127,42 +132,45 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f8k128(ConvArgs a, const unsig
     stab[k] = off;
   }
 
-  // the whole input halo, every channel block, as FP8 (zero outside the image)
+  // the whole input halo, every channel block, as FP8 (zero outside the
+  // image): each thread takes halo positions tid, tid + 256, ... and loads
+  // every channel block of them (the address math once per position)
   {
     const bf16* base0 = f8_view_base<bf16>(a.in0, img, in_plane * a.in0.cbt);
     const bf16* base1 = f8_view_base<bf16>(a.in1, img, in_plane * a.in1.cbt);
-    const int total = nblk * NPOS;
-    constexpr int U = 20;  // loads in flight per thread (all of them for up to 16 blocks of a 16 x 16 tile)
-    for (int i0 = tid; i0 < total; i0 += 256 * U) {
-      u4 v[U];
-      int h16 = 0;
+    constexpr int PP = (NPOS + 255) / 256;  // positions per thread
+    constexpr int U = 8;                    // blocks loaded together
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * 256;
-        v[u] = u4{0u, 0u, 0u, 0u};
-        if (i < total) {
-          const int blk = i / NPOS, pos = i - blk * NPOS;
-          const int py = pos / IW, px = pos - py * IW;
-          const int gy = iy0 + py, gx = ix0 + px;
-          if (gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w) {
-            const bool v0 = blk < a.nb0;
-            const bf16* src = v0 ? base0 + (size_t)(blk + a.in0.cb0) * in_plane
-                                 : base1 + (size_t)(blk - a.nb0 + a.in1.cb0) * in_plane;
-            v[u] = ldg(reinterpret_cast<const u4*>(src + ((size_t)gy * a.in_w + gx) * 8));
-            h16 |= ((a.in_f16 >> (v0 ? 0 : 1)) & 1) << u;
+    for (int pp = 0; pp < PP; ++pp) {
+      const int pos = tid + pp * 256;
+      if (pos >= NPOS) break;
+      const int py = pos / IW, px = pos - (pos / IW) * IW;
+      const int gy = iy0 + py, gx = ix0 + px;
+      const bool in = gy >= 0 && gy < a.in_h && gx >= 0 && gx < a.in_w;
+      const size_t off = in ? ((size_t)gy * a.in_w + gx) * 8 : 0;
+      for (int b0 = 0; b0 < nblk; b0 += U) {
+        u4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int blk = b0 + u;
+          v[u] = u4{0u, 0u, 0u, 0u};
+          if (in && blk < nblk) {
+            const bf16* src = blk < a.nb0 ? base0 + (size_t)(blk + a.in0.cb0) * in_plane
+                                          : base1 + (size_t)(blk - a.nb0 + a.in1.cb0) * in_plane;
+            v[u] = ldg(reinterpret_cast<const u4*>(src + off));
           }
         }
-      }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = i0 + u * 256;
-        if (i < total) {
-          float f[8];
-          if ((h16 >> u) & 1)
-            unpack8h(v[u], f);
-          else
-            load8(reinterpret_cast<const bf16*>(&v[u]), f);
-          reinterpret_cast<u2v*>(sA)[i] = pack8_fp8(f, inv_sa);
+        for (int u = 0; u < U; ++u) {
+          const int blk = b0 + u;
+          if (blk < nblk) {
+            float f[8];
+            if ((a.in_f16 >> (blk < a.nb0 ? 0 : 1)) & 1)
+              unpack8h(v[u], f);
+            else
+              load8(reinterpret_cast<const bf16*>(&v[u]), f);
+            reinterpret_cast<u2v*>(sA)[blk * NPOS + pos] = pack8_fp8_nosat(f, inv_sa);
+          }
         }
       }
     }
@@ -226,24 +234,46 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f8k128(ConvArgs a, const unsig
   float mx = 0.f;
   bf16* so = reinterpret_cast<bf16*>(smem) + (size_t)wave * (Q8_TW * NP);
   const size_t plane = (size_t)a.out_h * a.out_w;
+  // LeakyReLU as max(v, slope v) (0 <= slope <= 1); slope 1 = no activation
+  const float slope = a.lrelu ? a.slope : 1.f;
+  const bool track = a.aout != nullptr;
+  float osc[NB], bn[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int n = nb * 16 + lm;
+    osc[nb] = sa * a.wscale[n];
+    bn[nb] = n < a.cout ? a.b[n] : 0.f;
+  }
 #pragma unroll
   for (int mb = 0; mb < MR; ++mb) {
     const int oy = ty0 + wave * MR + mb;
     __syncthreads();
+    float y[NB][4];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int n = nb * 16 + lm;
-      const bool nok = n < a.cout;
-      const float osc = sa * a.wscale[n];
-      const float bn = nok ? a.b[n] : 0.f;
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int vv = 0; vv < 4; ++vv) {
-        const int px = 4 * lk + vv;
-        float v = acc[mb][nb][vv] * osc + bn;
-        if (a.lrelu) v = v >= 0.f ? v : a.slope * v;
-        if (nok && oy < a.out_h && tx0 + px < a.out_w) mx = fmaxf(mx, fabsf(v));
-        so[px * NP + n] = a.out_f16 ? __builtin_bit_cast(bf16, (f16)v) : f2bf(v);
+        const float v = fmaf(acc[mb][nb][vv], osc[nb], bn[nb]);
+        y[nb][vv] = fmaxf(v, slope * v);
       }
+    if (track && oy < a.out_h) {  // amax of the stored outputs (real channels, in the image)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv)
+          if (nb * 16 + lm < a.cout && tx0 + 4 * lk + vv < a.out_w) mx = fmaxf(mx, fabsf(y[nb][vv]));
+    }
+    if (a.out_f16) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv)
+          so[(4 * lk + vv) * NP + nb * 16 + lm] = __builtin_bit_cast(bf16, (f16)y[nb][vv]);
+    } else {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) so[(4 * lk + vv) * NP + nb * 16 + lm] = f2bf(y[nb][vv]);
     }
     __syncthreads();
     if (oy < a.out_h) {
