@@ -103,11 +103,28 @@ __global__ __launch_bounds__(256) void paper_reference_kernel(PaperArgs a) {
 
 constexpr int RW = 64, PPT = 12, RH = 4 * PPT;
 
+// Horizontal neighbours through the cross-lane data path (DPP wavefront
+// shifts; lane x holds column x of the region): the value of lane x - 1, and
+// of lane x + 1 (0 past the wavefront's ends, masked by the callers).
+__device__ inline float from_left(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ inline float from_right(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+// K iterations of the momentum solver on a RW x RH region (K-pixel halo on
+// each side, whose values go stale and are not written back).  Wave w holds
+// rows PPT w .. PPT w + PPT - 1 of the region in registers, one column per
+// lane: horizontal neighbours come from the neighbouring lanes, vertical ones
+// from the lane's own rows, except for a strip's first and last rows, whose
+// outer neighbours the adjacent waves publish in LDS each iteration (double
+// buffered by iteration parity: one barrier per iteration).
 __global__ __launch_bounds__(256) void paper_solve_kernel(PaperArgs a, const float* __restrict__ O,
                                                           const float* __restrict__ Oold,
                                                           float* __restrict__ On,
                                                           float* __restrict__ Onold, int K) {
-  __shared__ float sO[3][RH][RW + 1];
+  __shared__ float sx[2][4][2][3][RW];  // [parity][wave][first / last row][channel][column]
   const int tx = threadIdx.x & 63, tg = threadIdx.x >> 6;
   const int TWo = RW - 2 * K, THo = RH - 2 * K;
   const int img = blockIdx.z;
@@ -132,35 +149,51 @@ __global__ __launch_bounds__(256) void paper_solve_kernel(PaperArgs a, const flo
       r[k][c] = in ? a.R[q] : 0.f;
     }
   }
+  // in-image neighbours inside the region (outside the region the value is
+  // stale anyway and only feeds the discarded border)
+  const bool hx1 = gx + 1 < a.w && tx + 1 < RW, hx0 = gx > 0 && tx > 0;
 
   for (int it = 0; it < K; ++it) {
+    float(*ex)[2][3][RW] = sx[it & 1];
 #pragma unroll
-    for (int k = 0; k < PPT; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) sO[c][tg * PPT + k][tx] = o[k][c];
+    for (int c = 0; c < 3; ++c) {
+      ex[tg][0][c][tx] = o[0][c];
+      ex[tg][1][c][tx] = o[PPT - 1][c];
+    }
     __syncthreads();
+    float up[3], dn[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      up[c] = tg > 0 ? ex[tg - 1][1][c][tx] : 0.f;
+      dn[c] = tg < 3 ? ex[tg + 1][0][c][tx] : 0.f;
+    }
+    float no[PPT][3];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       const int ly = tg * PPT + k, gy = gy0 + k;
-      // in-image neighbours inside the region (outside the region the value
-      // is stale anyway and only feeds the discarded border)
-      const bool hx1 = gx + 1 < a.w && tx + 1 < RW, hx0 = gx > 0 && tx > 0;
       const bool hy1 = gy + 1 < a.h && ly + 1 < RH, hy0 = gy > 0 && ly > 0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float cen = o[k][c];
+        const float right = from_right(cen), left = from_left(cen);
+        const float below = k + 1 < PPT ? o[k + 1][c] : dn[c];
+        const float above = k > 0 ? o[k - 1][c] : up[c];
         float lap = 0.f;
-        if (hx1) lap += sO[c][ly][tx + 1] - cen;
-        if (hx0) lap += sO[c][ly][tx - 1] - cen;
-        if (hy1) lap += sO[c][ly + 1][tx] - cen;
-        if (hy0) lap += sO[c][ly - 1][tx] - cen;
+        if (hx1) lap += right - cen;
+        if (hx0) lap += left - cen;
+        if (hy1) lap += below - cen;
+        if (hy0) lap += above - cen;
         const float grad = -lap + wc[k] * cen - r[k][c];
-        const float nv = cen - a.eta * grad + a.kappa * (cen - oo[k][c]);
-        oo[k][c] = cen;
-        o[k][c] = nv;
+        no[k][c] = cen - a.eta * grad + a.kappa * (cen - oo[k][c]);
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PPT; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        oo[k][c] = o[k][c];
+        o[k][c] = no[k][c];
+      }
   }
 
   // write back the interior
