@@ -29,12 +29,15 @@
 // Lane l = 16 g + m transforms the 6x6 patch of tile m for channel g: its 36
 // values are exactly its A operands (A[m][k = g]) for the 36 GEMMs, so V
 // never touches LDS.  Its 36 B operands (the transformed weights of input g
-// and output m of its N block) are 144 contiguous bytes in global memory,
-// read straight into registers at the top of the chunk: the two waves of an
-// N block share them through L1/L2, and LDS carries only the halo.  The
-// accumulators of a lane hold all 36 positions of its 4 tiles, so the output
-// transform runs in registers; results go through LDS to whole 32-byte
-// channel-block stores.
+// and output m of its N block) are 144 contiguous bytes of the chunk's
+// 18 KB of transformed weights, which travel from global memory straight
+// into a second pair of LDS buffers (direct global-to-LDS loads, one chunk
+// ahead, no registers): the two waves of an N block read one copy.  A chunk
+// reads all its LDS operands first and only then issues the next chunk's
+// loads, so the matrix instructions never wait on memory.  The accumulators
+// of a lane hold all 36 positions of its 4 tiles, so the output transform
+// runs in registers; results go through LDS to whole 32-byte channel-block
+// stores.
 //
 // Work mapping: one workgroup per (image, region row, region column, channel
 // slice), slice fastest, consecutive work items on the same XCD, so the
@@ -101,9 +104,14 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
   constexpr int THREADS = C::THREADS, QY = C::QY, QX = C::QX, QHX = C::QHX, QRP = C::QRP,
                 QAP = C::QAP, QNA = C::QNA, QRA = C::QRA,
                 QSTAGE = C::QSTAGE;
-  // two stage buffers; after the K loop, 128 pixels x QOP per wave for the epilogue
-  constexpr int SMEM = 2 * QSTAGE > 2 * QM * 128 * QOP ? 2 * QSTAGE : 2 * QM * 128 * QOP;
-  __shared__ __attribute__((aligned(16))) float smem[SMEM];
+  // Two transformed-weight buffers and two halo stage buffers, as separate
+  // arrays: the compiler can then tell the weights' direct LDS loads from
+  // the halo reads and does not wait for those loads before every read.
+  // After the K loop the weight buffers hold the epilogue's 64 pixels x QOP
+  // per wave.
+  static_assert(2 * QM * 64 * QOP <= 2 * QUF, "epilogue exceeds the weight buffers");
+  __shared__ __attribute__((aligned(16))) float ubuf[2 * QUF];
+  __shared__ __attribute__((aligned(16))) float stage[2 * QSTAGE];
 
   // XCD-aware work id: block b runs on XCD b % 8; give each XCD a contiguous
   // range of work ids (a bijection of [0, total)).
@@ -148,11 +156,15 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
     off[j] = (cy * a.in_w + cx) * 8;
     inb |= (ok ? 1u : 0u) << j;
   }
+  // the two input views' image bases, read once (a view may hold a table
+  // of per-image pointers)
+  const float* const base0 = qview_base(a.in0, img, in_plane * a.in0.cbt) + (size_t)a.in0.cb0 * in_plane;
+  const float* const base1 =
+      a.nblk > a.nb0 ? qview_base(a.in1, img, in_plane * a.in1.cbt) + (size_t)a.in1.cb0 * in_plane : base0;
   auto fetch = [&](int ch) {
     const int b = ch >> 1;
-    const View& v = b < a.nb0 ? a.in0 : a.in1;
-    const int cb = (b < a.nb0 ? b : b - a.nb0) + v.cb0;
-    const float* src = qview_base(v, img, in_plane * v.cbt) + (size_t)cb * in_plane + (ch & 1) * 4;
+    const float* src = (b < a.nb0 ? base0 + (size_t)b * in_plane : base1 + (size_t)(b - a.nb0) * in_plane) +
+                       (ch & 1) * 4;
 #pragma unroll
     for (int j = 0; j < QRA; ++j) ra[j] = ldg(reinterpret_cast<const f4*>(src + off[j]));
   };
@@ -172,24 +184,43 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
     }
   };
 
+  // The chunk's transformed weights (QUF floats = 18 pieces of 1 KB) go
+  // straight from global memory into an LDS buffer (global_load_lds: lane l
+  // of a wave writes bytes 16 l .. 16 l + 15 of the wave's 1 KB piece), one
+  // chunk ahead of their use, without passing through registers.  Wave w
+  // loads pieces w, w + 4, ... (THREADS / 64 waves share the 18 pieces).
+  constexpr int NWAVE = THREADS / 64, UPIECES = QUF / 256;
+  auto fetch_u = [&](int ch, float* dst) {
+    const float* src = wslice + (size_t)ch * QUF + lane * 4;
+#pragma unroll
+    for (int kb = wave; kb < UPIECES; kb += NWAVE)
+      __builtin_amdgcn_global_load_lds(
+          reinterpret_cast<const void*>(src + kb * 256),
+          (__attribute__((address_space(3))) void*)(dst + kb * 256), 16, 0, 0);
+  };
+
   // this lane's tile (A row m = lm): tile row 2 mblk + lm / 8, column lm % 8;
   // its patch in channel plane lg
   const int aoff = lg * QAP + 4 * (2 * mblk + (lm >> 3)) * QRP + 4 * (lm & 7);
   // its 36 transformed weights (B[k = lg][n = lm] of every position)
-  const float* ulane = wslice + (size_t)(nb * 64 + lane) * 36;
+  const int uoff = (nb * 64 + lane) * 36;
 
+  fetch_u(0, ubuf);
   fetch(0);
-  stash(smem);
+  stash(stage);
+  __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0) (the weights' LDS loads) and lgkmcnt(0)
   __syncthreads();
   for (int ch = 0; ch < nch; ++ch) {
-    const float* st = smem + (ch & 1) * QSTAGE;
+    const float* st = stage + (ch & 1) * QSTAGE;
+    // All of the chunk's LDS reads come first: the compiler orders LDS reads
+    // after a pending direct LDS load behind a wait for it, so the next
+    // chunk's loads are issued only once this chunk's operands are read.
     f4 uq[9];
     {
-      const f4* up = reinterpret_cast<const f4*>(ulane + (size_t)ch * QUF);
+      const f4* up = reinterpret_cast<const f4*>(ubuf + (ch & 1) * QUF + uoff);
 #pragma unroll
-      for (int k = 0; k < 9; ++k) uq[k] = ldg(up + k);
+      for (int k = 0; k < 9; ++k) uq[k] = up[k];
     }
-    if (ch + 1 < nch) fetch(ch + 1);
     // the patch, then V = B^T d B (columns first, then rows)
     float d[6][6];
 #pragma unroll
@@ -202,6 +233,10 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
       d[i][3] = lo.w;
       d[i][4] = hi.x;
       d[i][5] = hi.y;
+    }
+    if (ch + 1 < nch) {
+      fetch(ch + 1);
+      fetch_u(ch + 1, ubuf + ((ch + 1) & 1) * QUF);
     }
     float tcol[6][6];  // tcol[p][j] = (B^T d)[p][j]
 #pragma unroll
@@ -228,23 +263,23 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
       acc[4 * k + 2] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[4 * k + 2], u.z, acc[4 * k + 2], 0, 0, 0);
       acc[4 * k + 3] = __builtin_amdgcn_mfma_f32_16x16x4f32(v[4 * k + 3], u.w, acc[4 * k + 3], 0, 0, 0);
     }
-    if (ch + 1 < nch) stash(smem + ((ch + 1) & 1) * QSTAGE);
+    if (ch + 1 < nch) stash(stage + ((ch + 1) & 1) * QSTAGE);
+    __builtin_amdgcn_s_waitcnt(0);  // the next chunk's weights have landed in LDS
     __syncthreads();
   }
 
   // ---- output transform, bias, LeakyReLU; through LDS to 32-byte block
   // stores.  Lane (lg, lm) holds tiles 4 lg + vv (vv = 0..3) of its M block
-  // for output channel sl * 32 + nb * 16 + lm.  Two passes of 8 tiles each
-  // (vv in {2 pass, 2 pass + 1}); tile k of a pass is 4 (k / 2) + 2 pass + k % 2.
-  float* so = smem + wave * (128 * QOP);
+  // for output channel sl * 32 + nb * 16 + lm.  Four passes of 4 tiles each
+  // (vv = pass); tile k of a pass is 4 k + pass.
+  float* so = ubuf + wave * (64 * QOP);
   const size_t plane = (size_t)a.out_h * a.out_w;
   const int n = sl * 32 + nb * 16 + lm;
   const float bn = n < a.cout ? a.b[n] : 0.f;
 #pragma unroll
-  for (int pass = 0; pass < 2; ++pass) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int vv = 2 * pass + h;
+  for (int pass = 0; pass < 4; ++pass) {
+    {
+      const int vv = pass;
       float tc4[4][6];  // (A^T M)[i][qq]
 #pragma unroll
       for (int qq = 0; qq < 6; ++qq) {
@@ -255,7 +290,7 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
 #pragma unroll
         for (int i = 0; i < 4; ++i) tc4[i][qq] = z[i];
       }
-      const int k = 2 * lg + h;  // tile of the pass
+      const int k = lg;  // tile of the pass
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         float z[4];
@@ -269,12 +304,12 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
       }
     }
     __syncthreads();
-    // 128 pixels x 2 blocks of 8 channels per wave
+    // 64 pixels x 2 blocks of 8 channels per wave
 #pragma unroll
-    for (int e = lane; e < 256; e += 64) {
+    for (int e = lane; e < 128; e += 64) {
       const int px = e >> 1, blk = e & 1;
       const int k = px >> 4, i = (px >> 2) & 3, jj = px & 3;
-      const int tile = 4 * (k >> 1) + 2 * pass + (k & 1);
+      const int tile = 4 * k + pass;
       const int oy = ty0 + 4 * (2 * mblk + (tile >> 3)) + i;
       const int ox = tx0 + 4 * (tile & 7) + jj;
       const int cblk = (sl * 32 + nb * 16) / 8 + blk;
