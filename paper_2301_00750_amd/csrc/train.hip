@@ -182,13 +182,8 @@ __global__ __launch_bounds__(256) void sum_kernel(const float* __restrict__ part
 // ---------------------------------------------------------------- weight gradient
 //
 // dW[o][g][tap] = sum over images and output pixels of dz[o](y, x) *
-// X[g](s y + p - 1, s x + q - 1) (zero outside).  A workgroup owns one block
-// of 8 output channels, one block of KB input channels (packed order) and a
-// range of row tiles (an image row, 64 output pixels); per tile it stages dz
-// [64][8] and the three input rows it needs in LDS.  Thread (tap, cg, pg)
-// accumulates an 8 x 4 block of (o, c) sums over pixels pg, pg + NPG, ...;
-// at the end the NPG pixel groups are reduced in LDS and the workgroup writes
-// its 8 x KB x 9 partial sums.
+// X[g](s y + p - 1, s x + q - 1) (zero outside), per pixel chunk as partial
+// sums, then added over the chunks in a fixed order.
 struct WgArgs {
   const float* dz;  // blocked, dz_cbt blocks per image, first block dz_cb0
   int dz_cbt, dz_cb0;
@@ -203,127 +198,184 @@ struct WgArgs {
 
 constexpr int WG_TW = 64;
 
-template <int KB>
-__global__ __launch_bounds__(256) void wgrad_kernel(WgArgs a) {
-  constexpr int NCG = KB / 4;
-  constexpr int NCOMBO = 9 * NCG;
-  constexpr int NPG = 256 / NCOMBO;
-  constexpr int XW = 2 * (WG_TW - 1) + 3;  // input columns (stride 2 bound)
-  __shared__ f4 sdz[WG_TW][2];
-  __shared__ f4 sx[3][XW][NCG];
-  __shared__ float red[256 * 16];
+// The chunk sums on the FP32 matrix cores (v_mfma_f32_16x16x4_f32), as a GEMM
+// with M = output channels (MB blocks of 16), N = (tap, input channel) and
+// K = output pixels: N block j is tap j = 3 p + q, its column n input
+// channel 16 cg + n of the workgroup's 16-channel group cg.  A workgroup owns
+// a range of row tiles (64 output pixels of one row), one channel group and
+// one group of MB output blocks (output channels 16 MB mg ...);
+// per tile it stages dz [64][16 MB] and the three input rows [3][cols][16] in
+// LDS (pitches chosen so a K step's 64 lanes read distinct banks), and wave w
+// takes K steps w, w + 4, w + 8, w + 12 (4 pixels each): one A read and nine
+// B reads feed 9 MB matrix instructions.  At the end the four waves' sums
+// are added in wave order and written as the chunk's partials
+// ([chunk][ob][cb][8][KB][9]).
+template <int MB>
+__global__ __launch_bounds__(256) void wgrad_mfma_kernel(WgArgs a, int KB, int cout, int cin_pad) {
+  constexpr int TW = WG_TW;
+  constexpr int PO = 32 * MB - 16;          // dz floats per pixel (16 mod 32)
+  constexpr int XWM = 2 * (TW - 1) + 3;     // input columns (stride 2 bound)
+  constexpr int PC = 16;                    // input floats per staged pixel
+  constexpr int NDZ = TW * PO, NX = 3 * XWM * PC;
+  static_assert(3 * 9 * 256 <= NDZ + NX, "wave reduction exceeds LDS");
+  __shared__ __attribute__((aligned(16))) float smem[NDZ + NX];
+  float* const sdz = smem;
+  float* const sx = smem + NDZ;
 
-  const int ob = blockIdx.y, cb = blockIdx.z;
+  const int cg = blockIdx.y;
+  const int obase = 16 * MB * blockIdx.z;  // first output channel of the group
+  const int ob0 = obase / 8, nobg = min(2 * MB, a.nob - ob0);
   const int s = a.stride;
-  const int xt = (a.wo + WG_TW - 1) / WG_TW;
+  const int xt = (a.wo + TW - 1) / TW;
   const long tiles = (long)a.n * a.ho * xt;
   const long per = (tiles + a.chunks - 1) / a.chunks;
   const long t0 = blockIdx.x * per, t1 = min(tiles, t0 + per);
-  const int tid = threadIdx.x;
-  const int combo = tid % NCOMBO, pg = tid / NCOMBO;
-  const int tap = combo % 9, cg = combo / 9;
-  const int p = tap / 3, q = tap % 3;
-  const bool active = pg < NPG;
-
-  const float* xb;
-  int xcbt, xblk;
-  if (cb < a.nb0) {
-    xb = a.x0; xcbt = a.x0_cbt; xblk = a.x0_cb0 + cb;
-  } else {
-    xb = a.x1; xcbt = a.x1_cbt; xblk = a.x1_cb0 + cb - a.nb0;
-  }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kg = lane >> 4, ln = lane & 15;
   const size_t Pi = (size_t)a.hi * a.wi, Po = (size_t)a.ho * a.wo;
+  const int ncol = s * (TW - 1) + 3;
 
-  float acc[8][4];
+  // output channels past the last block stay zero (the tiles never write them)
+  for (int e = tid; e < NDZ; e += 256) sdz[e] = 0.f;
+
+  f4 acc[MB][9];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int m = 0; m < MB; ++m)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+    for (int j = 0; j < 9; ++j) acc[m][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   for (long t = t0; t < t1; ++t) {
     const int img = (int)(t / ((long)a.ho * xt));
     const int rem = (int)(t - (long)img * a.ho * xt);
-    const int yo = rem / xt, x0 = (rem % xt) * WG_TW;
-    // dz tile: 64 pixels x 8 channels
-    for (int e = tid; e < WG_TW * 2; e += 256) {
-      const int px = e >> 1, h = e & 1;
-      const int xo = x0 + px;
+    const int yo = rem / xt, x0 = (rem % xt) * TW;
+    // dz: 64 pixels x the group's blocks x 2 halves of 4 channels
+    for (int e = tid; e < TW * nobg * 2; e += 256) {
+      const int h = e & 1, px = (e >> 1) % TW, obl = (e >> 1) / TW;
+      const int xo = x0 + px, ol = obl * 8 + 4 * h, o = obase + ol;
       f4 v = f4{0.f, 0.f, 0.f, 0.f};
       if (xo < a.wo)
-        v = *(reinterpret_cast<const f4*>(
-                  a.dz + (((size_t)img * a.dz_cbt + a.dz_cb0 + ob) * Po + (size_t)yo * a.wo + xo) * 8) +
+        v = *(reinterpret_cast<const f4*>(a.dz + (((size_t)img * a.dz_cbt + a.dz_cb0 + ob0 + obl) * Po +
+                                                  (size_t)yo * a.wo + xo) *
+                                                     8) +
               h);
-      sdz[px][h] = v;
+      if (o + 0 >= cout) v.x = 0.f;
+      if (o + 1 >= cout) v.y = 0.f;
+      if (o + 2 >= cout) v.z = 0.f;
+      if (o + 3 >= cout) v.w = 0.f;
+      *reinterpret_cast<f4*>(sdz + px * PO + ol) = v;
     }
-    // input rows s*yo - 1 .. s*yo + 1, columns s*x0 - 1 .. s*(x0 + 63) + 1
-    const int ncol = s * (WG_TW - 1) + 3;
-    for (int e = tid; e < 3 * ncol * NCG; e += 256) {
-      const int h = e % NCG, col = (e / NCG) % ncol, row = e / (NCG * ncol);
+    // input rows s yo - 1 .. s yo + 1, columns s x0 - 1 ..; 16 channels as 4 x 4
+    for (int e = tid; e < 3 * ncol * 4; e += 256) {
+      const int q4 = e & 3, col = (e >> 2) % ncol, row = (e >> 2) / ncol;
       const int yi = s * yo + row - 1, xi = s * x0 + col - 1;
+      const int g = cg * 16 + q4 * 4;
       f4 v = f4{0.f, 0.f, 0.f, 0.f};
-      if (yi >= 0 && yi < a.hi && xi >= 0 && xi < a.wi)
-        v = *(reinterpret_cast<const f4*>(
-                  xb + (((size_t)img * xcbt + xblk) * Pi + (size_t)yi * a.wi + xi) * KB) +
-              h);
-      sx[row][col][h] = v;
+      if (g < cin_pad && yi >= 0 && yi < a.hi && xi >= 0 && xi < a.wi) {
+        const int b = g / KB, off = g - b * KB;
+        const float* xb;
+        int xcbt, xblk;
+        if (b < a.nb0) {
+          xb = a.x0; xcbt = a.x0_cbt; xblk = a.x0_cb0 + b;
+        } else {
+          xb = a.x1; xcbt = a.x1_cbt; xblk = a.x1_cb0 + b - a.nb0;
+        }
+        v = *reinterpret_cast<const f4*>(xb + (((size_t)img * xcbt + xblk) * Pi + (size_t)yi * a.wi + xi) * KB +
+                                         off);
+      }
+      *reinterpret_cast<f4*>(sx + (row * XWM + col) * PC + q4 * 4) = v;
     }
     __syncthreads();
-    if (active) {
-      for (int px = pg; px < WG_TW; px += NPG) {
-        const f4 d0 = sdz[px][0], d1 = sdz[px][1];
-        const f4 xv = sx[p][s * px + q][cg];
-        const float dv[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
-        const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < TW / 16; ++i) {
+      const int px = 4 * (wave + 4 * i) + kg;  // this lane's pixel (K index)
+      float av[MB];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] += dv[i] * xs[j];
+      for (int m = 0; m < MB; ++m) av[m] = sdz[px * PO + m * 16 + ln];
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        const float bv = sx[((j / 3) * XWM + s * px + j % 3) * PC + ln];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m], bv, acc[m][j], 0, 0, 0);
       }
     }
     __syncthreads();
   }
 
-  // reduce the pixel groups: 4 output channels at a time through LDS
-  float* out = a.partial + (((size_t)blockIdx.x * a.nob + ob) * a.ncb + cb) * (8 * KB * 9);
+  // add the waves' sums in wave order; D[m = 4 kg + v][n = ln] of block
+  // (mb, j) is output channel obase + 16 mb + 4 kg + v, input channel
+  // 16 cg + ln, tap j
+  float* out = a.partial + (size_t)blockIdx.x * a.nob * 8 * cin_pad * 9;
+  float* red = smem;
 #pragma unroll
-  for (int i0 = 0; i0 < 8; i0 += 4) {
+  for (int m = 0; m < MB; ++m) {
+    if (wave > 0)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) red[(i * 4 + j) * 256 + tid] = active ? acc[i0 + i][j] : 0.f;
+      for (int j = 0; j < 9; ++j) *reinterpret_cast<f4*>(red + ((wave - 1) * 9 + j) * 256 + lane * 4) = acc[m][j];
     __syncthreads();
-    // value (i, j, combo): sum over pg of red[(i*4+j)*256 + pg*NCOMBO + combo]
-    for (int e = tid; e < 16 * NCOMBO; e += 256) {
-      const int ij = e / NCOMBO, cmb = e % NCOMBO;
-      float sum = 0.f;
-      for (int g = 0; g < NPG; ++g) sum += red[ij * 256 + g * NCOMBO + cmb];
-      const int i = ij / 4, j = ij % 4;
-      const int tp = cmb % 9, cgg = cmb / 9;
-      out[((i0 + i) * KB + cgg * 4 + j) * 9 + tp] = sum;
+    if (wave == 0) {
+      const int g = cg * 16 + ln;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        f4 v = acc[m][j];
+#pragma unroll
+        for (int w = 0; w < 3; ++w) {
+          const f4 r = *reinterpret_cast<const f4*>(red + (w * 9 + j) * 256 + lane * 4);
+          v.x += r.x;
+          v.y += r.y;
+          v.z += r.z;
+          v.w += r.w;
+        }
+        const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int o = obase + 16 * m + 4 * kg + k;
+          if (o < 8 * a.nob && g < cin_pad) {
+            const int cb = g / KB, gg = g - cb * KB;
+            out[(((size_t)(o / 8) * a.ncb + cb) * 8 + o % 8) * KB * 9 + gg * 9 + j] = vv[k];
+          }
+        }
+      }
     }
     __syncthreads();
   }
 }
 
-// grad[woff + (o cin + cmap[g]) 9 + tap] = sum over chunks of the partials
-__global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int chunks, int nob,
-                                    int ncb, int KB, int cout, int cin, int cin_pad,
-                                    const int* __restrict__ cmap, float* __restrict__ grad,
-                                    int woff) {
-  const size_t total = (size_t)cout * cin_pad * 9;
-  const size_t per_chunk = (size_t)nob * ncb * 8 * KB * 9;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int tap = (int)(e % 9);
-    const int g = (int)((e / 9) % cin_pad);
-    const int o = (int)(e / ((size_t)9 * cin_pad));
-    const int c = cmap[g];
-    if (c < 0) continue;
-    const size_t idx = (((size_t)(o / 8) * ncb + g / KB) * 8 + o % 8) * KB * 9 + (g % KB) * 9 + tap;
-    float sum = 0.f;
-    for (int k = 0; k < chunks; ++k) sum += partial[k * per_chunk + idx];
-    grad[woff + ((size_t)o * cin + c) * 9 + tap] = sum;
+// grad[woff + (o cin + cmap[g]) 9 + tap] = sum over chunks of the partials.
+// A workgroup takes 64 consecutive partial entries (lane = entry, so every
+// chunk's read is one contiguous 256-byte row); wave w adds chunks
+// [w per, (w + 1) per) in order, and wave 0 adds the four sums in wave order.
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ partial, int chunks,
+                                                           int nob, int ncb, int KB, int cout, int cin,
+                                                           int cin_pad, const int* __restrict__ cmap,
+                                                           float* __restrict__ grad, int woff) {
+  __shared__ float red[3][64];
+  const int per_chunk = nob * ncb * 8 * KB * 9;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  const int per = (chunks + 3) / 4, k0 = wave * per, k1 = min(chunks, k0 + per);
+  float sum = 0.f;
+  if (e < per_chunk) {
+    const float* src = partial + e;
+    int k = k0;
+    for (; k + 4 <= k1; k += 4) {
+      const float v0 = src[(size_t)k * per_chunk], v1 = src[(size_t)(k + 1) * per_chunk];
+      const float v2 = src[(size_t)(k + 2) * per_chunk], v3 = src[(size_t)(k + 3) * per_chunk];
+      sum = (((sum + v0) + v1) + v2) + v3;
+    }
+    for (; k < k1; ++k) sum += src[(size_t)k * per_chunk];
   }
+  if (wave > 0) red[wave - 1][lane] = sum;
+  __syncthreads();
+  if (wave > 0 || e >= per_chunk) return;
+  sum = ((sum + red[0][lane]) + red[1][lane]) + red[2][lane];
+  // entry e = (((ob ncb + cb) 8 + oo) KB + gg) 9 + tap
+  const int tap = e % 9, gg = (e / 9) % KB, oo = (e / (9 * KB)) % 8, cb = (e / (72 * KB)) % ncb;
+  const int ob = e / (72 * KB * ncb);
+  const int o = ob * 8 + oo, g = cb * KB + gg;
+  if (o >= cout || g >= cin_pad) return;
+  const int c = cmap[g];
+  if (c < 0) return;
+  grad[woff + ((size_t)o * cin + c) * 9 + tap] = sum;
 }
 
 // bias gradient: per (chunk, output channel) partial sums of dz, then a
@@ -356,13 +408,22 @@ __global__ __launch_bounds__(256) void bgrad_kernel(const float* __restrict__ dz
   if (threadIdx.x < 8) partial[((size_t)blockIdx.x * nob + ob) * 8 + threadIdx.x] = red[0][threadIdx.x];
 }
 
-__global__ void bgrad_reduce_kernel(const float* __restrict__ partial, int chunks, int nob,
-                                    int cout, float* __restrict__ grad, int boff) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= cout) return;
+// one workgroup per output channel: thread k adds chunks k, k + 256, ... in
+// order, then a fixed-order tree over the 256 sums
+__global__ __launch_bounds__(256) void bgrad_reduce_kernel(const float* __restrict__ partial, int chunks,
+                                                           int nob, int cout, float* __restrict__ grad,
+                                                           int boff) {
+  __shared__ float red[256];
+  const int o = blockIdx.x;
   float sum = 0.f;
-  for (int k = 0; k < chunks; ++k) sum += partial[((size_t)k * nob + o / 8) * 8 + o % 8];
-  grad[boff + o] = sum;
+  for (int k = threadIdx.x; k < chunks; k += 256) sum += partial[((size_t)k * nob + o / 8) * 8 + o % 8];
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && o < cout) grad[boff + o] = red[0];
 }
 
 // ---------------------------------------------------------------- stride-2 data gradient
@@ -822,27 +883,31 @@ int wgrad(tc_trainer* t, const TLayer& Ly, const float* dz, int dz_cbt, int dz_c
   a.nob = (Ly.cout + 7) / 8;
   a.ncb = Ly.cin_pad / KB;
   const long tiles = (long)n * ho * ((wo + WG_TW - 1) / WG_TW);
-  long chunks = 2048 / (a.nob * a.ncb);
-  if (chunks < 1) chunks = 1;
-  if (chunks > tiles) chunks = tiles;
+  const size_t chunk_b = (size_t)a.nob * a.ncb * 8 * KB * 9 * sizeof(float);
+  // matrix cores: groups of up to 3 output blocks of 16 and of 16 input
+  // channels; about 1024 workgroups over the pixel chunks
+  const int mbt = (Ly.cout + 15) / 16, mb = std::min(mbt, 3), nmg = (mbt + mb - 1) / mb;
+  const int ngrp = (Ly.cin_pad + 15) / 16;
+  long chunks = 1024 / (ngrp * nmg);
+  chunks = std::max(1L, std::min({chunks, tiles, (long)(t->wpart_b / chunk_b)}));
   a.chunks = (int)chunks;
-  if ((size_t)a.chunks * a.nob * a.ncb * 8 * KB * 9 * sizeof(float) > t->wpart_b)
-    return TC_ERR_WORKSPACE;
   a.partial = t->wpart;
-  dim3 grid(a.chunks, a.nob, a.ncb);
-  if (KB == 8)
-    wgrad_kernel<8><<<grid, 256, 0, s>>>(a);
+  dim3 grid(a.chunks, ngrp, nmg);
+  if (mb == 1)
+    wgrad_mfma_kernel<1><<<grid, 256, 0, s>>>(a, KB, Ly.cout, Ly.cin_pad);
+  else if (mb == 2)
+    wgrad_mfma_kernel<2><<<grid, 256, 0, s>>>(a, KB, Ly.cout, Ly.cin_pad);
   else
-    wgrad_kernel<4><<<grid, 256, 0, s>>>(a);
+    wgrad_mfma_kernel<3><<<grid, 256, 0, s>>>(a, KB, Ly.cout, Ly.cin_pad);
   if (hipGetLastError() != hipSuccess) return TC_ERR_HIP;
-  wgrad_reduce_kernel<<<grid1((size_t)Ly.cout * Ly.cin_pad * 9), 256, 0, s>>>(
-      t->wpart, a.chunks, a.nob, a.ncb, KB, Ly.cout, Ly.cin, Ly.cin_pad, Ly.cmap, t->G,
-      (int)Ly.woff);
+  const int per_chunk = a.nob * a.ncb * 8 * KB * 9;
+  wgrad_reduce_kernel<<<(per_chunk + 63) / 64, 256, 0, s>>>(t->wpart, a.chunks, a.nob, a.ncb, KB, Ly.cout,
+                                                            Ly.cin, Ly.cin_pad, Ly.cmap, t->G, (int)Ly.woff);
   // bias
   const int bch = 256;
   bgrad_kernel<<<dim3(bch, a.nob), 256, 0, s>>>(dz, dz_cbt, dz_cb0, a.nob, n, ho * wo, bch,
                                                 t->bpart);
-  bgrad_reduce_kernel<<<1, 128, 0, s>>>(t->bpart, bch, a.nob, Ly.cout, t->G, (int)Ly.boff);
+  bgrad_reduce_kernel<<<Ly.cout, 256, 0, s>>>(t->bpart, bch, a.nob, Ly.cout, t->G, (int)Ly.boff);
   return hipGetLastError() == hipSuccess ? TC_OK : TC_ERR_HIP;
 }
 
@@ -1216,7 +1281,7 @@ int tc_trainer_create(const tc_net_desc* desc, const float* host_weights, size_t
   }
   t->cpart_b = cp;
   t->cpart = A(cp);
-  t->wpart_b = (size_t)2048 * 8 * 8 * 9 * 4 * 2;
+  t->wpart_b = (size_t)32 << 20;
   t->wpart = A(t->wpart_b);
   t->bpart = A((size_t)256 * 16 * 8 * 4);
   t->lchunks = 256;
