@@ -615,29 +615,59 @@ __global__ void cv_bwd_f2w_kernel(const float* __restrict__ dZ, int dz_cbt, int 
   }
 }
 
-// Warp backward: dF2 (scattered with atomics) and
+// Warp backward: dF2 (scattered) and
 // dU = dZ[U] + dflow + sum_c dF2w_c d F2w_c / dU  (U null: zero flow and no
-// dU).
-__global__ void warp_bwd_kernel(const float* __restrict__ dF2w, const float* __restrict__ F2,
-                                const float* __restrict__ U, int n, int nb, int h, int w,
-                                float* __restrict__ dF2, const float* __restrict__ dZ, int dz_cbt,
-                                int u_cb, int u_c, const float* __restrict__ dflow,
-                                float* __restrict__ dU) {
+// dU).  A workgroup owns a 16 x 16 pixel tile.  The in-image bilinear taps of
+// its pixels span a window of the source image; when the window has at most
+// WB_WIN positions, each 8-channel block's tap contributions are first added
+// in LDS (LDS atomics), and the window is then added to dF2 with one global
+// atomic per nonzero entry: about 9 global atomics per pixel and block for a
+// smooth flow instead of 32.  Wider windows scatter straight to dF2.
+constexpr int WB_T = 16, WB_WIN = 40 * 40;
+
+__global__ __launch_bounds__(256) void warp_bwd_kernel(const float* __restrict__ dF2w, const float* __restrict__ F2,
+                                                       const float* __restrict__ U, int n, int nb, int h, int w,
+                                                       float* __restrict__ dF2, const float* __restrict__ dZ,
+                                                       int dz_cbt, int u_cb, int u_c,
+                                                       const float* __restrict__ dflow, float* __restrict__ dU) {
+  __shared__ float win[WB_WIN * 8];
+  __shared__ int bb[4];  // window: x min, x max, y min, y max
+  const int x = blockIdx.x * WB_T + (threadIdx.x & 15), y = blockIdx.y * WB_T + (threadIdx.x >> 4);
+  const int img = blockIdx.z;
+  const bool in = x < w && y < h;
   const size_t P = (size_t)h * w;
-  const size_t total = (size_t)n * P;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const int img = (int)(i / P);
-    const int pix = (int)(i - (size_t)img * P);
-    const int y = pix / w, x = pix - (pix / w) * w;
-    const float2 u = U ? reinterpret_cast<const float2*>(U)[i] : make_float2(0.f, 0.f);
-    const Taps t = taps_of(x, y, u.x, u.y);
-    float gx = 0.f, gy = 0.f;
-    for (int b = 0; b < nb; ++b) {
+  const int pix = in ? y * w + x : 0;
+  const size_t i = (size_t)img * P + pix;
+  const float2 u = in && U ? reinterpret_cast<const float2*>(U)[i] : make_float2(0.f, 0.f);
+  const Taps t = taps_of(x, y, u.x, u.y);
+  if (threadIdx.x == 0) {
+    bb[0] = w;
+    bb[1] = -1;
+    bb[2] = h;
+    bb[3] = -1;
+  }
+  __syncthreads();
+  if (in) {
+    atomicMin(&bb[0], max(t.x0, 0));
+    atomicMax(&bb[1], min(t.x0 + 1, w - 1));
+    atomicMin(&bb[2], max(t.y0, 0));
+    atomicMax(&bb[3], min(t.y0 + 1, h - 1));
+  }
+  __syncthreads();
+  const int wx0 = bb[0], wy0 = bb[2];
+  const int ww = bb[1] - wx0 + 1, wh = bb[3] - wy0 + 1;
+  const bool agg = ww > 0 && wh > 0 && ww * wh <= WB_WIN;
+  const int nwin = agg ? ww * wh * 8 : 0;
+
+  float gx = 0.f, gy = 0.f;
+  for (int b = 0; b < nb; ++b) {
+    const float* fb = F2 + ((size_t)img * nb + b) * P * 8;
+    float* db = dF2 + ((size_t)img * nb + b) * P * 8;
+    for (int e = threadIdx.x; e < nwin; e += 256) win[e] = 0.f;
+    if (agg) __syncthreads();
+    if (in) {
       float g[8];
       load8(dF2w + (((size_t)img * nb + b) * P + pix) * 8, g);
-      const float* fb = F2 + ((size_t)img * nb + b) * P * 8;
-      float* db = dF2 + ((size_t)img * nb + b) * P * 8;
       float F[4][8];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -646,10 +676,19 @@ __global__ void warp_bwd_kernel(const float* __restrict__ dF2w, const float* __r
         if (ok) {
           load8(fb + ((size_t)yi * w + xi) * 8, F[k]);
           const float wt = ((k & 1) ? t.ax : 1.f - t.ax) * ((k >> 1) ? t.ay : 1.f - t.ay);
-          float* d = db + ((size_t)yi * w + xi) * 8;
+          if (wt != 0.f) {
+            if (agg) {
+              float* d = win + ((yi - wy0) * ww + (xi - wx0)) * 8;
 #pragma unroll
-          for (int c = 0; c < 8; ++c)
-            if (wt != 0.f && g[c] != 0.f) unsafeAtomicAdd(d + c, wt * g[c]);
+              for (int c = 0; c < 8; ++c)
+                if (g[c] != 0.f) atomicAdd(d + c, wt * g[c]);
+            } else {
+              float* d = db + ((size_t)yi * w + xi) * 8;
+#pragma unroll
+              for (int c = 0; c < 8; ++c)
+                if (g[c] != 0.f) unsafeAtomicAdd(d + c, wt * g[c]);
+            }
+          }
         } else {
 #pragma unroll
           for (int c = 0; c < 8; ++c) F[k][c] = 0.f;
@@ -662,12 +701,23 @@ __global__ void warp_bwd_kernel(const float* __restrict__ dF2w, const float* __r
         gy += g[c] * ((1.f - t.ax) * (F[2][c] - F[0][c]) + t.ax * (F[3][c] - F[1][c]));
       }
     }
-    if (dU) {
-      const float* zu = dZ + (((size_t)img * dz_cbt + u_cb) * P + pix) * 8;
-      const float* df = dflow + i * 8;
-      reinterpret_cast<float2*>(dU)[i] =
-          make_float2(gx + zu[u_c] + df[0], gy + zu[u_c + 1] + df[1]);
+    if (agg) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < nwin; e += 256) {
+        const float v = win[e];
+        if (v != 0.f) {
+          const int pos = e >> 3, c = e & 7;
+          const int yy = wy0 + pos / ww, xx = wx0 + pos % ww;
+          unsafeAtomicAdd(db + ((size_t)yy * w + xx) * 8 + c, v);
+        }
+      }
+      __syncthreads();
     }
+  }
+  if (in && dU) {
+    const float* zu = dZ + (((size_t)img * dz_cbt + u_cb) * P + pix) * 8;
+    const float* df = dflow + i * 8;
+    reinterpret_cast<float2*>(dU)[i] = make_float2(gx + zu[u_c] + df[0], gy + zu[u_c + 1] + df[1]);
   }
 }
 
@@ -1068,7 +1118,7 @@ int backward(tc_trainer* t, const float* T, int n, hipStream_t s) {
                                                                 w, d.radius, t->dW2);
     // warp backward; U = 2 up2(flow_{l+1}) below the top level
     const int ucb = cb + t->ncv / 8, uc = t->ncv % 8;
-    warp_bwd_kernel<<<grid1((size_t)n * P), 256, 0, s>>>(
+    warp_bwd_kernel<<<dim3((w + WB_T - 1) / WB_T, (h + WB_T - 1) / WB_T, n), 256, 0, s>>>(
         t->dW2, V.feat + n * fimg, l < t->L ? V.U : nullptr, n, cb, h, w, V.dfeat + n * fimg,
         t->dZ, zt, ucb, uc, V.dflow, l < t->L ? t->dU : nullptr);
     if (l < t->L) {

@@ -74,6 +74,48 @@ def test_gradient_vs_oracle(tc):
     assert worst[0][0] <= 1e-3
 
 
+def test_gradient_vs_oracle_wide_flows(tc):
+    """Head gain 50 makes the level-1 flows large and spatially varying: the
+    warp backward then meets both its paths (16 x 16 tiles whose taps fit a
+    40 x 40 window, added in LDS first, and wider tiles scattered straight to
+    the gradient); the oracle's own level-1 flow shows that both occur."""
+    d = dict(synth.load_desc("student"), head_gain=50.0)
+    blob = synth.he_weights(d)
+    A, B, T = batch(2, 96, 128, 11)
+    wts = {k: (torch.from_numpy(w).double(), torch.from_numpy(b).double())
+           for k, (w, b) in O.unpack_weights(blob, d).items()}
+    U = (2.0 * S.up2(S.student_flows(A.double(), B.double(), wts, d)[1])).numpy()
+    n, _, h, w = U.shape
+    wide = fit = 0
+    for i in range(n):
+        for ty in range(0, h, 16):
+            for tx in range(0, w, 16):
+                ys, xs = np.mgrid[ty:min(ty + 16, h), tx:min(tx + 16, w)]
+                x0 = np.floor(xs + U[i, 0, ty:ty + 16, tx:tx + 16]).astype(int)
+                y0 = np.floor(ys + U[i, 1, ty:ty + 16, tx:tx + 16]).astype(int)
+                ww = min(x0.max() + 1, w - 1) - max(x0.min(), 0) + 1
+                wh = min(y0.max() + 1, h - 1) - max(y0.min(), 0) + 1
+                if ww > 0 and wh > 0 and ww * wh <= 1600:
+                    fit += 1
+                else:
+                    wide += 1
+    say(f"[train] gradient 2 x 96x128, head gain 50: level-1 |U| <= {np.abs(U).max():.1f}, "
+        f"tiles fitting the window {fit}, wider {wide}")
+    assert fit > 0 and wide > 0
+    tr = tc.Trainer(d, blob, 2, 96, 128)
+    loss = tr.grad(A.cuda().contiguous(), B.cuda().contiguous(), T.cuda().contiguous())
+    g = tr.copy(1).cpu().double().numpy()
+    lref, gref = S.loss_and_grad(blob.astype(np.float64), A.double(), B.double(), T.double(), d)
+    say(f"   loss gpu={float(loss):.7f} oracle={lref:.7f}")
+    assert abs(float(loss) - lref) <= 1e-5 * abs(lref)
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    worst = max(np.abs(g[a:b] - gref[a:b]).max() / max(np.abs(gref[a:b]).max(), 1e-12)
+                for _, a, b in layer_slices(d, blob))
+    say(f"   gradient relative L2 error {rel:.2e}, worst layer {worst:.2e}")
+    assert rel <= 1e-4
+    assert worst <= 1e-3
+
+
 def test_adamw_steps_vs_oracle(tc):
     d = synth.load_desc("student")
     blob = synth.he_weights(d)
