@@ -210,22 +210,24 @@ constexpr int WG_TW = 64;
 // B reads feed 9 MB matrix instructions.  At the end the four waves' sums
 // are added in wave order and written as the chunk's partials
 // ([chunk][ob][cb][8][KB][9]).
-template <int MB>
-__global__ __launch_bounds__(256) void wgrad_mfma_kernel(WgArgs a, int KB, int cout, int cin_pad) {
+template <int MB, int S>
+__global__ __launch_bounds__(256, 2) void wgrad_mfma_kernel(WgArgs a, int KB, int cout, int cin_pad) {
   constexpr int TW = WG_TW;
   constexpr int PO = 32 * MB - 16;          // dz floats per pixel (16 mod 32)
-  constexpr int XWM = 2 * (TW - 1) + 3;     // input columns (stride 2 bound)
+  constexpr int XWM = S * (TW - 1) + 3;     // input columns
   constexpr int PC = 16;                    // input floats per staged pixel
   constexpr int NDZ = TW * PO, NX = 3 * XWM * PC;
-  static_assert(3 * 9 * 256 <= NDZ + NX, "wave reduction exceeds LDS");
-  __shared__ __attribute__((aligned(16))) float smem[NDZ + NX];
+  constexpr int RDZ = TW * 2 * MB * 2 / 256;         // dz float4 per thread and tile
+  constexpr int RX = (3 * XWM * 4 + 255) / 256;      // input float4 per thread and tile
+  static_assert(TW * 2 * MB * 2 % 256 == 0, "dz tile split");
+  constexpr int SMEM = NDZ + NX > 3 * 9 * 256 ? NDZ + NX : 3 * 9 * 256;  // staging, or the wave reduction
+  __shared__ __attribute__((aligned(16))) float smem[SMEM];
   float* const sdz = smem;
   float* const sx = smem + NDZ;
 
   const int cg = blockIdx.y;
   const int obase = 16 * MB * blockIdx.z;  // first output channel of the group
   const int ob0 = obase / 8, nobg = min(2 * MB, a.nob - ob0);
-  const int s = a.stride;
   const int xt = (a.wo + TW - 1) / TW;
   const long tiles = (long)a.n * a.ho * xt;
   const long per = (tiles + a.chunks - 1) / a.chunks;
@@ -233,10 +235,6 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(WgArgs a, int KB, int c
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kg = lane >> 4, ln = lane & 15;
   const size_t Pi = (size_t)a.hi * a.wi, Po = (size_t)a.ho * a.wo;
-  const int ncol = s * (TW - 1) + 3;
-
-  // output channels past the last block stay zero (the tiles never write them)
-  for (int e = tid; e < NDZ; e += 256) sdz[e] = 0.f;
 
   f4 acc[MB][9];
 #pragma unroll
@@ -244,16 +242,22 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(WgArgs a, int KB, int c
 #pragma unroll
     for (int j = 0; j < 9; ++j) acc[m][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  for (long t = t0; t < t1; ++t) {
+  // A tile's loads go to registers one tile ahead (rdz: 64 pixels x the
+  // group's blocks x 2 halves of 4 output channels; rx: 3 input rows x
+  // XWM columns x 4 quarters of the 16 channels), zero outside the image,
+  // past the output channels and past the packed input channels.
+  f4 rdz[RDZ], rx[RX];
+  auto load = [&](long t) {
     const int img = (int)(t / ((long)a.ho * xt));
     const int rem = (int)(t - (long)img * a.ho * xt);
     const int yo = rem / xt, x0 = (rem % xt) * TW;
-    // dz: 64 pixels x the group's blocks x 2 halves of 4 channels
-    for (int e = tid; e < TW * nobg * 2; e += 256) {
+#pragma unroll
+    for (int j = 0; j < RDZ; ++j) {
+      const int e = tid + 256 * j;
       const int h = e & 1, px = (e >> 1) % TW, obl = (e >> 1) / TW;
-      const int xo = x0 + px, ol = obl * 8 + 4 * h, o = obase + ol;
+      const int xo = x0 + px, o = obase + obl * 8 + 4 * h;
       f4 v = f4{0.f, 0.f, 0.f, 0.f};
-      if (xo < a.wo)
+      if (obl < nobg && xo < a.wo)
         v = *(reinterpret_cast<const f4*>(a.dz + (((size_t)img * a.dz_cbt + a.dz_cb0 + ob0 + obl) * Po +
                                                   (size_t)yo * a.wo + xo) *
                                                      8) +
@@ -262,15 +266,16 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(WgArgs a, int KB, int c
       if (o + 1 >= cout) v.y = 0.f;
       if (o + 2 >= cout) v.z = 0.f;
       if (o + 3 >= cout) v.w = 0.f;
-      *reinterpret_cast<f4*>(sdz + px * PO + ol) = v;
+      rdz[j] = v;
     }
-    // input rows s yo - 1 .. s yo + 1, columns s x0 - 1 ..; 16 channels as 4 x 4
-    for (int e = tid; e < 3 * ncol * 4; e += 256) {
-      const int q4 = e & 3, col = (e >> 2) % ncol, row = (e >> 2) / ncol;
-      const int yi = s * yo + row - 1, xi = s * x0 + col - 1;
+#pragma unroll
+    for (int j = 0; j < RX; ++j) {
+      const int e = tid + 256 * j;
+      const int q4 = e & 3, col = (e >> 2) % XWM, row = (e >> 2) / XWM;
+      const int yi = S * yo + row - 1, xi = S * x0 + col - 1;
       const int g = cg * 16 + q4 * 4;
       f4 v = f4{0.f, 0.f, 0.f, 0.f};
-      if (g < cin_pad && yi >= 0 && yi < a.hi && xi >= 0 && xi < a.wi) {
+      if (row < 3 && g < cin_pad && yi >= 0 && yi < a.hi && xi >= 0 && xi < a.wi) {
         const int b = g / KB, off = g - b * KB;
         const float* xb;
         int xcbt, xblk;
@@ -282,9 +287,26 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(WgArgs a, int KB, int c
         v = *reinterpret_cast<const f4*>(xb + (((size_t)img * xcbt + xblk) * Pi + (size_t)yi * a.wi + xi) * KB +
                                          off);
       }
-      *reinterpret_cast<f4*>(sx + (row * XWM + col) * PC + q4 * 4) = v;
+      rx[j] = v;
+    }
+  };
+
+  if (t0 < t1) load(t0);
+  for (long t = t0; t < t1; ++t) {
+#pragma unroll
+    for (int j = 0; j < RDZ; ++j) {
+      const int e = tid + 256 * j;
+      const int h = e & 1, px = (e >> 1) % TW, obl = (e >> 1) / TW;
+      *reinterpret_cast<f4*>(sdz + px * PO + obl * 8 + 4 * h) = rdz[j];
+    }
+#pragma unroll
+    for (int j = 0; j < RX; ++j) {
+      const int e = tid + 256 * j;
+      const int q4 = e & 3, col = (e >> 2) % XWM, row = (e >> 2) / XWM;
+      if (row < 3) *reinterpret_cast<f4*>(sx + (row * XWM + col) * PC + q4 * 4) = rx[j];
     }
     __syncthreads();
+    if (t + 1 < t1) load(t + 1);
 #pragma unroll
     for (int i = 0; i < TW / 16; ++i) {
       const int px = 4 * (wave + 4 * i) + kg;  // this lane's pixel (K index)
@@ -293,7 +315,7 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(WgArgs a, int KB, int c
       for (int m = 0; m < MB; ++m) av[m] = sdz[px * PO + m * 16 + ln];
 #pragma unroll
       for (int j = 0; j < 9; ++j) {
-        const float bv = sx[((j / 3) * XWM + s * px + j % 3) * PC + ln];
+        const float bv = sx[((j / 3) * XWM + S * px + j % 3) * PC + ln];
 #pragma unroll
         for (int m = 0; m < MB; ++m) acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[m], bv, acc[m][j], 0, 0, 0);
       }
@@ -525,15 +547,19 @@ __global__ void warp_kernel(const float* __restrict__ F2, const float* __restric
 __global__ void cv_grad_kernel(float* __restrict__ dZ, int dz_cbt, int cv_cb0,
                                const float* __restrict__ Z, int zcb, int n, int P, int ncv,
                                float slope, float invC) {
-  const size_t total = (size_t)n * P * ncv;
+  // memory order: (image, block of 8 channels, pixel, channel in block)
+  const int nbk = (ncv + 7) / 8;
+  const size_t total = (size_t)n * nbk * P * 8;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
-    const int k = (int)(e % ncv);
-    const size_t r = e / ncv;
-    const int p = (int)(r % P);
-    const int img = (int)(r / P);
-    const float z = Z[(((size_t)img * zcb + k / 8) * P + p) * 8 + k % 8];
-    float& d = dZ[(((size_t)img * dz_cbt + cv_cb0 + k / 8) * P + p) * 8 + k % 8];
+    const int c = (int)(e & 7);
+    const size_t r = e >> 3;
+    const size_t p = r % P;
+    const size_t ib = r / P;
+    const int blk = (int)(ib % nbk), img = (int)(ib / nbk);
+    if (blk * 8 + c >= ncv) continue;
+    const float z = Z[(((size_t)img * zcb + blk) * P + p) * 8 + c];
+    float& d = dZ[(((size_t)img * dz_cbt + cv_cb0 + blk) * P + p) * 8 + c];
     d = d * (z >= 0.f ? 1.f : slope) * invC;
   }
 }
@@ -943,12 +969,16 @@ int wgrad(tc_trainer* t, const TLayer& Ly, const float* dz, int dz_cbt, int dz_c
   a.chunks = (int)chunks;
   a.partial = t->wpart;
   dim3 grid(a.chunks, ngrp, nmg);
+  const bool s1 = Ly.stride == 1;
   if (mb == 1)
-    wgrad_mfma_kernel<1><<<grid, 256, 0, s>>>(a, KB, Ly.cout, Ly.cin_pad);
+    s1 ? wgrad_mfma_kernel<1, 1><<<grid, 256, 0, s>>>(a, KB, Ly.cout, Ly.cin_pad)
+       : wgrad_mfma_kernel<1, 2><<<grid, 256, 0, s>>>(a, KB, Ly.cout, Ly.cin_pad);
   else if (mb == 2)
-    wgrad_mfma_kernel<2><<<grid, 256, 0, s>>>(a, KB, Ly.cout, Ly.cin_pad);
+    s1 ? wgrad_mfma_kernel<2, 1><<<grid, 256, 0, s>>>(a, KB, Ly.cout, Ly.cin_pad)
+       : wgrad_mfma_kernel<2, 2><<<grid, 256, 0, s>>>(a, KB, Ly.cout, Ly.cin_pad);
   else
-    wgrad_mfma_kernel<3><<<grid, 256, 0, s>>>(a, KB, Ly.cout, Ly.cin_pad);
+    s1 ? wgrad_mfma_kernel<3, 1><<<grid, 256, 0, s>>>(a, KB, Ly.cout, Ly.cin_pad)
+       : wgrad_mfma_kernel<3, 2><<<grid, 256, 0, s>>>(a, KB, Ly.cout, Ly.cin_pad);
   if (hipGetLastError() != hipSuccess) return TC_ERR_HIP;
   const int per_chunk = a.nob * a.ncb * 8 * KB * 9;
   wgrad_reduce_kernel<<<(per_chunk + 63) / 64, 256, 0, s>>>(t->wpart, a.chunks, a.nob, a.ncb, KB, Ly.cout,
@@ -1108,7 +1138,7 @@ int backward(tc_trainer* t, const float* T, int n, hipStream_t s) {
     TT(wgrad(t, Ld[0], t->dH1, d0b, 0, V.feat, cb, 0, cb, V.Z, t->zcb, 0, n, h, w, h, w, s));
     TT(dgrad(t, Ld[0], t->dH1, d0b, 0, t->dZ, zt, 0, n, h, w, s));
     // cost volume -> F1 and the warped F2
-    cv_grad_kernel<<<grid1((size_t)n * P * t->ncv), 256, 0, s>>>(
+    cv_grad_kernel<<<grid1((size_t)n * P * ((t->ncv + 7) / 8) * 8), 256, 0, s>>>(
         t->dZ, zt, cb, V.Z, t->zcb, n, P, t->ncv, slope, 1.f / C);
     warp_kernel<<<grid1((size_t)n * P), 256, 0, s>>>(V.feat + n * fimg, l < t->L ? V.U : nullptr,
                                                      n, cb, h, w, t->W2);
