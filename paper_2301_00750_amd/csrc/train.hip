@@ -564,37 +564,61 @@ __global__ void cv_grad_kernel(float* __restrict__ dZ, int dz_cbt, int cv_cb0,
   }
 }
 
-// dF1(x) += dZ[F1](x) + sum_k g_k(x) F2w(x + d_k)
-__global__ void cv_bwd_f1_kernel(const float* __restrict__ dZ, int dz_cbt, int cv_cb0,
-                                 const float* __restrict__ F2w, int nb, int n, int h, int w,
-                                 int R, float* __restrict__ dF1) {
+// dF1(x) += dZ[F1](x) + sum_k g_k(x) F2w(x + d_k).  A workgroup owns a
+// 16 x 16 pixel tile: each pixel's 81 g_k sit in registers, and each 8-channel
+// block's F2w over the tile and its 4-pixel halo is staged in LDS (zero
+// outside the image, which drops the out-of-image displacements).
+constexpr int CV_R = 4, CV_T = 16, CV_H = CV_T + 2 * CV_R, CV_NK = (2 * CV_R + 1) * (2 * CV_R + 1);
+
+__global__ __launch_bounds__(256) void cv_bwd_f1_kernel(const float* __restrict__ dZ, int dz_cbt, int cv_cb0,
+                                                        const float* __restrict__ F2w, int nb, int n, int h,
+                                                        int w, float* __restrict__ dF1) {
+  __shared__ f4 sf[CV_H * CV_H * 2];  // [position][two halves of the block]
+  const int tx = threadIdx.x & (CV_T - 1), ty = threadIdx.x / CV_T;
+  const int x0 = blockIdx.x * CV_T, y0 = blockIdx.y * CV_T, img = blockIdx.z;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool in = x < w && y < h;
   const size_t P = (size_t)h * w;
-  const size_t total = (size_t)n * P * nb;
-  const int D = 2 * R + 1;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int b = (int)(e % nb);
-    const size_t r = e / nb;
-    const int pix = (int)(r % P);
-    const int img = (int)(r / P);
-    const int y = pix / w, x = pix - (pix / w) * w;
+  const int pix = in ? y * w + x : 0;
+  float g[CV_NK];
+  {
+    const float* gb = dZ + ((size_t)img * dz_cbt + cv_cb0) * P * 8 + (size_t)pix * 8;
+#pragma unroll
+    for (int kb = 0; kb < (CV_NK + 7) / 8; ++kb) {
+      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (in) load8(gb + (size_t)kb * P * 8, v);
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (kb * 8 + c < CV_NK) g[kb * 8 + c] = v[c];
+    }
+  }
+  for (int b = 0; b < nb; ++b) {
+    const float* fb = F2w + ((size_t)img * nb + b) * P * 8;
+    __syncthreads();
+    for (int e = threadIdx.x; e < CV_H * CV_H * 2; e += 256) {
+      const int hf = e & 1, pos = e >> 1;
+      const int yy = y0 - CV_R + pos / CV_H, xx = x0 - CV_R + pos % CV_H;
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};
+      if (yy >= 0 && yy < h && xx >= 0 && xx < w) v = ldg(reinterpret_cast<const f4*>(fb + ((size_t)yy * w + xx) * 8) + hf);
+      sf[e] = v;
+    }
+    __syncthreads();
+    if (!in) continue;
     float acc[8];
     load8(dZ + (((size_t)img * dz_cbt + b) * P + pix) * 8, acc);
-    const float* gbase = dZ + ((size_t)img * dz_cbt + cv_cb0) * P * 8;
-    const float* fbase = F2w + ((size_t)img * nb + b) * P * 8;
-    for (int dy = -R; dy <= R; ++dy) {
-      const int yy = y + dy;
-      if (yy < 0 || yy >= h) continue;
-      for (int dx = -R; dx <= R; ++dx) {
-        const int xx = x + dx;
-        if (xx < 0 || xx >= w) continue;
-        const int k = (dy + R) * D + (dx + R);
-        const float g = gbase[((size_t)(k / 8) * P + pix) * 8 + k % 8];
-        float v[8];
-        load8(fbase + ((size_t)yy * w + xx) * 8, v);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] += g * v[c];
-      }
+    for (int k = 0; k < CV_NK; ++k) {
+      const int dy = k / (2 * CV_R + 1), dx = k % (2 * CV_R + 1);
+      const int pos = (ty + dy) * CV_H + tx + dx;
+      const f4 a0 = sf[2 * pos], a1 = sf[2 * pos + 1];
+      acc[0] += g[k] * a0.x;
+      acc[1] += g[k] * a0.y;
+      acc[2] += g[k] * a0.z;
+      acc[3] += g[k] * a0.w;
+      acc[4] += g[k] * a1.x;
+      acc[5] += g[k] * a1.y;
+      acc[6] += g[k] * a1.z;
+      acc[7] += g[k] * a1.w;
     }
     float* dst = dF1 + (((size_t)img * nb + b) * P + pix) * 8;
     float cur[8];
@@ -605,39 +629,64 @@ __global__ void cv_bwd_f1_kernel(const float* __restrict__ dZ, int dz_cbt, int c
   }
 }
 
-// dF2w(y) = sum_k g_k(y - d_k) F1(y - d_k)
-__global__ void cv_bwd_f2w_kernel(const float* __restrict__ dZ, int dz_cbt, int cv_cb0,
-                                  const float* __restrict__ F1, int nb, int n, int h, int w,
-                                  int R, float* __restrict__ dF2w) {
+// dF2w(y) = sum_k g_k(y - d_k) F1(y - d_k).  A workgroup owns a 16 x 16
+// pixel tile; per 8-channel block of F1 it stages F1 over the tile and its
+// 4-pixel halo in LDS, then, one block of 8 displacements at a time, the
+// displacements' g over the same window (both zero outside the image, which
+// drops the out-of-image sources), and gathers.
+__global__ __launch_bounds__(256) void cv_bwd_f2w_kernel(const float* __restrict__ dZ, int dz_cbt, int cv_cb0,
+                                                         const float* __restrict__ F1, int nb, int n, int h,
+                                                         int w, float* __restrict__ dF2w) {
+  __shared__ f4 sf[CV_H * CV_H * 2];       // F1 block: [position][two halves]
+  __shared__ float sg[CV_H * CV_H * 8];    // g of 8 displacements: [position][8]
+  const int tx = threadIdx.x & (CV_T - 1), ty = threadIdx.x / CV_T;
+  const int x0 = blockIdx.x * CV_T, y0 = blockIdx.y * CV_T, img = blockIdx.z;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool in = x < w && y < h;
   const size_t P = (size_t)h * w;
-  const size_t total = (size_t)n * P * nb;
-  const int D = 2 * R + 1;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int b = (int)(e % nb);
-    const size_t r = e / nb;
-    const int pix = (int)(r % P);
-    const int img = (int)(r / P);
-    const int y = pix / w, x = pix - (pix / w) * w;
+  const float* gbase = dZ + ((size_t)img * dz_cbt + cv_cb0) * P * 8;
+  for (int b = 0; b < nb; ++b) {
+    const float* fb = F1 + ((size_t)img * nb + b) * P * 8;
+    __syncthreads();
+    for (int e = threadIdx.x; e < CV_H * CV_H * 2; e += 256) {
+      const int hf = e & 1, pos = e >> 1;
+      const int yy = y0 - CV_R + pos / CV_H, xx = x0 - CV_R + pos % CV_H;
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};
+      if (yy >= 0 && yy < h && xx >= 0 && xx < w) v = ldg(reinterpret_cast<const f4*>(fb + ((size_t)yy * w + xx) * 8) + hf);
+      sf[e] = v;
+    }
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const float* gbase = dZ + ((size_t)img * dz_cbt + cv_cb0) * P * 8;
-    const float* fbase = F1 + ((size_t)img * nb + b) * P * 8;
-    for (int dy = -R; dy <= R; ++dy) {
-      const int yy = y - dy;
-      if (yy < 0 || yy >= h) continue;
-      for (int dx = -R; dx <= R; ++dx) {
-        const int xx = x - dx;
-        if (xx < 0 || xx >= w) continue;
-        const int k = (dy + R) * D + (dx + R);
-        const size_t q = (size_t)yy * w + xx;
-        const float g = gbase[((size_t)(k / 8) * P + q) * 8 + k % 8];
-        float v[8];
-        load8(fbase + q * 8, v);
+    for (int kb = 0; kb < (CV_NK + 7) / 8; ++kb) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < CV_H * CV_H * 2; e += 256) {
+        const int hf = e & 1, pos = e >> 1;
+        const int yy = y0 - CV_R + pos / CV_H, xx = x0 - CV_R + pos % CV_H;
+        f4 v = f4{0.f, 0.f, 0.f, 0.f};
+        if (yy >= 0 && yy < h && xx >= 0 && xx < w)
+          v = ldg(reinterpret_cast<const f4*>(gbase + ((size_t)kb * P + (size_t)yy * w + xx) * 8) + hf);
+        *reinterpret_cast<f4*>(sg + pos * 8 + hf * 4) = v;
+      }
+      __syncthreads();
+      if (!in) continue;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc[c] += g * v[c];
+      for (int j = 0; j < 8; ++j) {
+        const int k = kb * 8 + j;
+        if (k >= CV_NK) break;
+        // source y - d_k with d_k = (k / 9 - 4, k % 9 - 4), in window coordinates
+        const int pos = (ty + 2 * CV_R - k / (2 * CV_R + 1)) * CV_H + tx + 2 * CV_R - k % (2 * CV_R + 1);
+        const float gv = sg[pos * 8 + j];
+        const f4 a0 = sf[2 * pos], a1 = sf[2 * pos + 1];
+        acc[0] += gv * a0.x;
+        acc[1] += gv * a0.y;
+        acc[2] += gv * a0.z;
+        acc[3] += gv * a0.w;
+        acc[4] += gv * a1.x;
+        acc[5] += gv * a1.y;
+        acc[6] += gv * a1.z;
+        acc[7] += gv * a1.w;
       }
     }
-    store8(dF2w + (((size_t)img * nb + b) * P + pix) * 8, acc);
+    if (in) store8(dF2w + (((size_t)img * nb + b) * P + (size_t)y * w + x) * 8, acc);
   }
 }
 
@@ -1142,10 +1191,10 @@ int backward(tc_trainer* t, const float* T, int n, hipStream_t s) {
         t->dZ, zt, cb, V.Z, t->zcb, n, P, t->ncv, slope, 1.f / C);
     warp_kernel<<<grid1((size_t)n * P), 256, 0, s>>>(V.feat + n * fimg, l < t->L ? V.U : nullptr,
                                                      n, cb, h, w, t->W2);
-    cv_bwd_f1_kernel<<<grid1((size_t)n * P * cb), 256, 0, s>>>(t->dZ, zt, cb, t->W2, cb, n, h, w,
-                                                               d.radius, V.dfeat);
-    cv_bwd_f2w_kernel<<<grid1((size_t)n * P * cb), 256, 0, s>>>(t->dZ, zt, cb, V.feat, cb, n, h,
-                                                                w, d.radius, t->dW2);
+    cv_bwd_f1_kernel<<<dim3((w + CV_T - 1) / CV_T, (h + CV_T - 1) / CV_T, n), 256, 0, s>>>(
+        t->dZ, zt, cb, t->W2, cb, n, h, w, V.dfeat);
+    cv_bwd_f2w_kernel<<<dim3((w + CV_T - 1) / CV_T, (h + CV_T - 1) / CV_T, n), 256, 0, s>>>(
+        t->dZ, zt, cb, V.feat, cb, n, h, w, t->dW2);
     // warp backward; U = 2 up2(flow_{l+1}) below the top level
     const int ucb = cb + t->ncv / 8, uc = t->ncv % 8;
     warp_bwd_kernel<<<dim3((w + WB_T - 1) / WB_T, (h + WB_T - 1) / WB_T, n), 256, 0, s>>>(
