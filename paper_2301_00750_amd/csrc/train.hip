@@ -542,37 +542,18 @@ __global__ void warp_kernel(const float* __restrict__ F2, const float* __restric
   }
 }
 
-// g_k = dZ[CV_k] * lrelu'(CV_k) / C, in place (channels 0..80 of the CV
-// blocks of dZ; the U channels 81, 82 are left as they are)
-__global__ void cv_grad_kernel(float* __restrict__ dZ, int dz_cbt, int cv_cb0,
-                               const float* __restrict__ Z, int zcb, int n, int P, int ncv,
-                               float slope, float invC) {
-  // memory order: (image, block of 8 channels, pixel, channel in block)
-  const int nbk = (ncv + 7) / 8;
-  const size_t total = (size_t)n * nbk * P * 8;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e & 7);
-    const size_t r = e >> 3;
-    const size_t p = r % P;
-    const size_t ib = r / P;
-    const int blk = (int)(ib % nbk), img = (int)(ib / nbk);
-    if (blk * 8 + c >= ncv) continue;
-    const float z = Z[(((size_t)img * zcb + blk) * P + p) * 8 + c];
-    float& d = dZ[(((size_t)img * dz_cbt + cv_cb0 + blk) * P + p) * 8 + c];
-    d = d * (z >= 0.f ? 1.f : slope) * invC;
-  }
-}
-
-// dF1(x) += dZ[F1](x) + sum_k g_k(x) F2w(x + d_k).  A workgroup owns a
+// dF1(x) += dZ[F1](x) + sum_k g_k(x) F2w(x + d_k), with g_k = dZ[cv_k] times
+// the LeakyReLU slope at Z[cv_k] and 1 / C (the cost volume's mean over the
+// channels, Sec. 3.2 correlation), formed where it is read.  A workgroup owns a
 // 16 x 16 pixel tile: each pixel's 81 g_k sit in registers, and each 8-channel
 // block's F2w over the tile and its 4-pixel halo is staged in LDS (zero
 // outside the image, which drops the out-of-image displacements).
 constexpr int CV_R = 4, CV_T = 16, CV_H = CV_T + 2 * CV_R, CV_NK = (2 * CV_R + 1) * (2 * CV_R + 1);
 
 __global__ __launch_bounds__(256) void cv_bwd_f1_kernel(const float* __restrict__ dZ, int dz_cbt, int cv_cb0,
-                                                        const float* __restrict__ F2w, int nb, int n, int h,
-                                                        int w, float* __restrict__ dF1) {
+                                                        const float* __restrict__ Z, int zcb, float slope,
+                                                        float invC, const float* __restrict__ F2w, int nb,
+                                                        int n, int h, int w, float* __restrict__ dF1) {
   __shared__ f4 sf[CV_H * CV_H * 2];  // [position][two halves of the block]
   const int tx = threadIdx.x & (CV_T - 1), ty = threadIdx.x / CV_T;
   const int x0 = blockIdx.x * CV_T, y0 = blockIdx.y * CV_T, img = blockIdx.z;
@@ -583,13 +564,17 @@ __global__ __launch_bounds__(256) void cv_bwd_f1_kernel(const float* __restrict_
   float g[CV_NK];
   {
     const float* gb = dZ + ((size_t)img * dz_cbt + cv_cb0) * P * 8 + (size_t)pix * 8;
+    const float* zb = Z + (size_t)img * zcb * P * 8 + (size_t)pix * 8;
 #pragma unroll
     for (int kb = 0; kb < (CV_NK + 7) / 8; ++kb) {
-      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      if (in) load8(gb + (size_t)kb * P * 8, v);
+      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (in) {
+        load8(gb + (size_t)kb * P * 8, v);
+        load8(zb + (size_t)kb * P * 8, z);
+      }
 #pragma unroll
       for (int c = 0; c < 8; ++c)
-        if (kb * 8 + c < CV_NK) g[kb * 8 + c] = v[c];
+        if (kb * 8 + c < CV_NK) g[kb * 8 + c] = v[c] * (z[c] >= 0.f ? invC : slope * invC);
     }
   }
   for (int b = 0; b < nb; ++b) {
@@ -629,14 +614,15 @@ __global__ __launch_bounds__(256) void cv_bwd_f1_kernel(const float* __restrict_
   }
 }
 
-// dF2w(y) = sum_k g_k(y - d_k) F1(y - d_k).  A workgroup owns a 16 x 16
+// dF2w(y) = sum_k g_k(y - d_k) F1(y - d_k), g_k as above.  A workgroup owns a 16 x 16
 // pixel tile; per 8-channel block of F1 it stages F1 over the tile and its
 // 4-pixel halo in LDS, then, one block of 8 displacements at a time, the
 // displacements' g over the same window (both zero outside the image, which
 // drops the out-of-image sources), and gathers.
 __global__ __launch_bounds__(256) void cv_bwd_f2w_kernel(const float* __restrict__ dZ, int dz_cbt, int cv_cb0,
-                                                         const float* __restrict__ F1, int nb, int n, int h,
-                                                         int w, float* __restrict__ dF2w) {
+                                                         const float* __restrict__ Z, int zcb, float slope,
+                                                         float invC, const float* __restrict__ F1, int nb,
+                                                         int n, int h, int w, float* __restrict__ dF2w) {
   __shared__ f4 sf[CV_H * CV_H * 2];       // F1 block: [position][two halves]
   __shared__ float sg[CV_H * CV_H * 8];    // g of 8 displacements: [position][8]
   const int tx = threadIdx.x & (CV_T - 1), ty = threadIdx.x / CV_T;
@@ -645,6 +631,7 @@ __global__ __launch_bounds__(256) void cv_bwd_f2w_kernel(const float* __restrict
   const bool in = x < w && y < h;
   const size_t P = (size_t)h * w;
   const float* gbase = dZ + ((size_t)img * dz_cbt + cv_cb0) * P * 8;
+  const float* zbase = Z + (size_t)img * zcb * P * 8;
   for (int b = 0; b < nb; ++b) {
     const float* fb = F1 + ((size_t)img * nb + b) * P * 8;
     __syncthreads();
@@ -662,8 +649,15 @@ __global__ __launch_bounds__(256) void cv_bwd_f2w_kernel(const float* __restrict
         const int hf = e & 1, pos = e >> 1;
         const int yy = y0 - CV_R + pos / CV_H, xx = x0 - CV_R + pos % CV_H;
         f4 v = f4{0.f, 0.f, 0.f, 0.f};
-        if (yy >= 0 && yy < h && xx >= 0 && xx < w)
-          v = ldg(reinterpret_cast<const f4*>(gbase + ((size_t)kb * P + (size_t)yy * w + xx) * 8) + hf);
+        if (yy >= 0 && yy < h && xx >= 0 && xx < w) {
+          const size_t q = ((size_t)kb * P + (size_t)yy * w + xx) * 8;
+          const f4 d = ldg(reinterpret_cast<const f4*>(gbase + q) + hf);
+          const f4 z = ldg(reinterpret_cast<const f4*>(zbase + q) + hf);
+          v.x = d.x * (z.x >= 0.f ? invC : slope * invC);
+          v.y = d.y * (z.y >= 0.f ? invC : slope * invC);
+          v.z = d.z * (z.z >= 0.f ? invC : slope * invC);
+          v.w = d.w * (z.w >= 0.f ? invC : slope * invC);
+        }
         *reinterpret_cast<f4*>(sg + pos * 8 + hf * 4) = v;
       }
       __syncthreads();
@@ -1187,14 +1181,12 @@ int backward(tc_trainer* t, const float* T, int n, hipStream_t s) {
     TT(wgrad(t, Ld[0], t->dH1, d0b, 0, V.feat, cb, 0, cb, V.Z, t->zcb, 0, n, h, w, h, w, s));
     TT(dgrad(t, Ld[0], t->dH1, d0b, 0, t->dZ, zt, 0, n, h, w, s));
     // cost volume -> F1 and the warped F2
-    cv_grad_kernel<<<grid1((size_t)n * P * ((t->ncv + 7) / 8) * 8), 256, 0, s>>>(
-        t->dZ, zt, cb, V.Z, t->zcb, n, P, t->ncv, slope, 1.f / C);
     warp_kernel<<<grid1((size_t)n * P), 256, 0, s>>>(V.feat + n * fimg, l < t->L ? V.U : nullptr,
                                                      n, cb, h, w, t->W2);
     cv_bwd_f1_kernel<<<dim3((w + CV_T - 1) / CV_T, (h + CV_T - 1) / CV_T, n), 256, 0, s>>>(
-        t->dZ, zt, cb, t->W2, cb, n, h, w, V.dfeat);
+        t->dZ, zt, cb, V.Z, t->zcb, slope, 1.f / C, t->W2, cb, n, h, w, V.dfeat);
     cv_bwd_f2w_kernel<<<dim3((w + CV_T - 1) / CV_T, (h + CV_T - 1) / CV_T, n), 256, 0, s>>>(
-        t->dZ, zt, cb, V.feat, cb, n, h, w, t->dW2);
+        t->dZ, zt, cb, V.Z, t->zcb, slope, 1.f / C, V.feat, cb, n, h, w, t->dW2);
     // warp backward; U = 2 up2(flow_{l+1}) below the top level
     const int ucb = cb + t->ncv / 8, uc = t->ncv % 8;
     warp_bwd_kernel<<<dim3((w + WB_T - 1) / WB_T, (h + WB_T - 1) / WB_T, n), 256, 0, s>>>(
