@@ -77,6 +77,39 @@ __global__ void pack_dgrad_kernel(const float* __restrict__ blob, int woff, int 
   }
 }
 
+// F(4x4, 3x3) Winograd weights U = G g G^T of a stride-1 trainer conv, in
+// the F(4x4) kernel's layout [32-output slice][chunk of 4 inputs][16-output
+// block][lane 16 (input % 4) + output % 16][36 positions] (G: Lavin and
+// Gray's F(4x4, 3x3) filter transform, applied in double).  One thread per
+// (conv output oc < nout, conv input ic < nin).  Forward: the kernel of blob
+// output oc and packed input ic; data gradient (dgrad != 0): conv output =
+// packed forward input g = oc, conv input = forward output o = ic, kernel
+// flipped.  Entries past the channels are zero.
+__global__ void pack_wino4_kernel(const float* __restrict__ blob, int woff, int cout, int cin,
+                                  const int* __restrict__ cmap, int cin_pad_f, int dgrad, int nout,
+                                  int nin, float* __restrict__ out) {
+  const double G[6][3] = {{1.0 / 4, 0.0, 0.0},           {-1.0 / 6, -1.0 / 6, -1.0 / 6},
+                          {-1.0 / 6, 1.0 / 6, -1.0 / 6}, {1.0 / 24, 1.0 / 12, 1.0 / 6},
+                          {1.0 / 24, -1.0 / 12, 1.0 / 6}, {0.0, 0.0, 1.0}};
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nout * nin) return;
+  const int oc = e / nin, ic = e % nin;
+  const int o = dgrad ? ic : oc, g = dgrad ? oc : ic;
+  const int c = g < cin_pad_f ? cmap[g] : -1;
+  const bool ok = o < cout && c >= 0;
+  double k[9];
+  for (int tap = 0; tap < 9; ++tap)
+    k[tap] = ok ? (double)blob[woff + ((size_t)o * cin + c) * 9 + (dgrad ? 8 - tap : tap)] : 0.0;
+  double Gg[6][3];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 3; ++j) Gg[i][j] = G[i][0] * k[j] + G[i][1] * k[3 + j] + G[i][2] * k[6 + j];
+  const int sl = oc / 32, nbk = (oc % 32) / 16, m = oc % 16, chunk = ic / 4, lane = 16 * (ic % 4) + m;
+  float* dst = out + ((((size_t)sl * (nin / 4) + chunk) * 2 + nbk) * 64 + lane) * 36;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j)
+      dst[6 * i + j] = (float)(Gg[i][0] * G[j][0] + Gg[i][1] * G[j][1] + Gg[i][2] * G[j][2]);
+}
+
 // ---------------------------------------------------------------- elementwise
 
 // dst (blocks [cb_d, cb_d + nb) of a cbt_d-block buffer) =
@@ -890,6 +923,8 @@ struct TLayer {
   int* cmap;                               // device, cin_pad entries
   float *w, *b;                            // device, packed forward weights and bias
   float* wd;                               // device, packed data-gradient weights (stride 1)
+  float* wu4 = nullptr;                    // device, F(4x4) Winograd forward weights, or null
+  float* wud4 = nullptr;                   // device, F(4x4) Winograd data-gradient weights, or null
   int dcin, dnp;                           // data-gradient conv: input channels (pad 8), np
 };
 
@@ -924,7 +959,7 @@ namespace {
 int tconv(const tc_trainer* t, const float* w, const float* b, int cout, int np, int nchunks,
           int kc, const View& in0, int nb0, const View& in1, int in_h, int in_w, float* out,
           int out_cbt, int out_cb0, int compact, const float* add, int out_h, int out_w, int relu,
-          int n, int stride, hipStream_t s) {
+          int n, int stride, hipStream_t s, const float* wu4 = nullptr) {
   ConvArgs a;
   memset(&a, 0, sizeof(a));
   a.in0 = in0;
@@ -950,7 +985,13 @@ int tconv(const tc_trainer* t, const float* w, const float* b, int cout, int np,
   a.n = n;
   a.partial = t->cpart;
   hipError_t e;
-  if (cout == 2 && compact && stride == 1 && kc == 8) {
+  if (wu4) {
+    // F(4x4) Winograd weights packed for C_out rounded up to 32
+    a.np = (cout + 31) / 32 * 32;
+    a.splits = 1;
+    a.cps = nchunks;
+    e = launch_conv3x3_wino4(a, wu4, s);
+  } else if (cout == 2 && compact && stride == 1 && kc == 8) {
     a.splits = 1;
     a.cps = nchunks;
     e = launch_head(a, s);
@@ -1039,7 +1080,7 @@ int dgrad(tc_trainer* t, const TLayer& Ly, const float* dz, int dz_cbt, int dz_c
           int out_cbt, int out_cb0, int n, int h, int w, hipStream_t s) {
   return tconv(t, Ly.wd, t->zbias, Ly.cin_pad, Ly.dnp, Ly.dcin / 8, 8, view(dz, dz_cbt, dz_cb0),
                Ly.dcin / 8, view(dz, dz_cbt, dz_cb0), h, w, out, out_cbt, out_cb0, 0, nullptr, h,
-               w, 0, n, 1, s);
+               w, 0, n, 1, s, Ly.wud4);
 }
 
 #define TT(x)                      \
@@ -1060,6 +1101,16 @@ int pack_all(tc_trainer* t, hipStream_t s) {
     if (Ly.wd)
       pack_dgrad_kernel<<<grid1((size_t)Ly.dcin * 9 * Ly.dnp), 256, 0, s>>>(
           t->P, (int)Ly.woff, Ly.cout, Ly.cin, Ly.dcin, Ly.dnp, Ly.cmap, Ly.cin_pad, Ly.wd);
+    if (Ly.wu4) {
+      const int nout = (Ly.cout + 31) / 32 * 32;
+      pack_wino4_kernel<<<(nout * Ly.cin_pad + 255) / 256, 256, 0, s>>>(
+          t->P, (int)Ly.woff, Ly.cout, Ly.cin, Ly.cmap, Ly.cin_pad, 0, nout, Ly.cin_pad, Ly.wu4);
+    }
+    if (Ly.wud4) {
+      const int nout = (Ly.cin_pad + 31) / 32 * 32;
+      pack_wino4_kernel<<<(nout * Ly.dcin + 255) / 256, 256, 0, s>>>(
+          t->P, (int)Ly.woff, Ly.cout, Ly.cin, Ly.cmap, Ly.cin_pad, 1, nout, Ly.dcin, Ly.wud4);
+    }
   };
   for (int l = 1; l <= t->L; ++l) {
     pk(t->pyr[l - 1][0]);
@@ -1122,11 +1173,13 @@ int forward(tc_trainer* t, const float* A, const float* B, int n, hipStream_t s)
     const TLayer* Ld = t->dec[l - 1];
     TT(tconv(t, Ld[0].w, Ld[0].b, Ld[0].cout, Ld[0].np, Ld[0].cin_pad / 8, 8,
              view(V.feat, V.C / 8), V.C / 8, view(V.Z, t->zcb), V.h, V.w, V.H1, d0b, 0, 0, nullptr,
-             V.h, V.w, 1, n, 1, s));
+             V.h, V.w, 1, n, 1, s, Ld[0].wu4));
     TT(tconv(t, Ld[1].w, Ld[1].b, Ld[1].cout, Ld[1].np, Ld[1].cin_pad / 8, 8, view(V.H1, d0b),
-             d0b, view(V.H1, d0b), V.h, V.w, V.H23, d23b, 0, 0, nullptr, V.h, V.w, 1, n, 1, s));
+             d0b, view(V.H1, d0b), V.h, V.w, V.H23, d23b, 0, 0, nullptr, V.h, V.w, 1, n, 1, s,
+             Ld[1].wu4));
     TT(tconv(t, Ld[2].w, Ld[2].b, Ld[2].cout, Ld[2].np, Ld[2].cin_pad / 8, 8, view(V.H23, d23b),
-             d1b, view(V.H23, d23b), V.h, V.w, V.H23, d23b, d1b, 0, nullptr, V.h, V.w, 1, n, 1, s));
+             d1b, view(V.H23, d23b), V.h, V.w, V.H23, d23b, d1b, 0, nullptr, V.h, V.w, 1, n, 1, s,
+             Ld[2].wu4));
     TT(tconv(t, Ld[3].w, Ld[3].b, 2, Ld[3].np, Ld[3].cin_pad / 8, 8, view(V.H23, d23b), d23b,
              view(V.H23, d23b), V.h, V.w, V.flow, 0, 0, 1, Ul, V.h, V.w, 0, n, 1, s));
   }
@@ -1368,6 +1421,20 @@ int tc_trainer_create(const tc_net_desc* desc, const float* host_weights, size_t
     V.flow = A((size_t)n * 2 * P * 4);
     V.dflow = A((size_t)n * 8 * P * 4);
     V.dfeat = A((size_t)n2 * V.C * P * 4);
+  }
+  // F(4x4) Winograd for the decoder convs of levels with at least 128
+  // regions of 16 x 32 output pixels per image, where rounding the conv's
+  // outputs up to 32 adds at most a third (c1 and c2 forward; c1, c2 and c3
+  // data gradient at the student's sizes)
+  for (int l = 1; l <= t->L; ++l) {
+    const Level& V = t->lv[l];
+    if ((long)((V.w + 31) / 32) * ((V.h + 15) / 16) < 128) continue;
+    auto fits = [](int nout) { return 3 * ((nout + 31) / 32 * 32) <= 4 * nout; };
+    for (int k = 0; k < 3; ++k) {
+      TLayer& Ly = t->dec[l - 1][k];
+      if (fits(Ly.cout)) Ly.wu4 = A((size_t)(Ly.cout + 31) / 32 * 32 * Ly.cin_pad * 36 * 4);
+      if (Ly.wd && fits(Ly.cin_pad)) Ly.wud4 = A((size_t)(Ly.cin_pad + 31) / 32 * 32 * Ly.dcin * 36 * 4);
+    }
   }
   int maxC = 0;
   for (int l = 0; l < t->L; ++l) maxC = std::max(maxC, desc->ch[l]);

@@ -116,6 +116,30 @@ def test_gradient_vs_oracle_wide_flows(tc):
     assert worst <= 1e-3
 
 
+def test_gradient_vs_oracle_winograd_level():
+    """At 512 x 1024 level 1 (256 x 512) has 256 regions of 16 x 32 pixels, so
+    the trainer runs its c1 and c2 forward and its c1, c2 and c3 data
+    gradients there through the F(4x4) Winograd conv (weights transformed on
+    the device from the current blob every call); level 2 stays direct."""
+    from paper_2301_00750_amd import tcflow as tc
+    d = synth.load_desc("student")
+    blob = synth.he_weights(d)
+    A, B, T = batch(1, 512, 1024, 21)
+    say("[train] gradient 1 x 512x1024 (Winograd on level 1)")
+    tr = tc.Trainer(d, blob, 1, 512, 1024)
+    loss = tr.grad(A.cuda().contiguous(), B.cuda().contiguous(), T.cuda().contiguous())
+    g = tr.copy(1).cpu().double().numpy()
+    lref, gref = S.loss_and_grad(blob.astype(np.float64), A.double(), B.double(), T.double(), d)
+    say(f"   loss gpu={float(loss):.7f} oracle={lref:.7f}")
+    assert abs(float(loss) - lref) <= 1e-5 * abs(lref)
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    worst = max(np.abs(g[a:b] - gref[a:b]).max() / max(np.abs(gref[a:b]).max(), 1e-12)
+                for _, a, b in layer_slices(d, blob))
+    say(f"   gradient relative L2 error {rel:.2e}, worst layer {worst:.2e}")
+    assert rel <= 1e-4
+    assert worst <= 1e-3
+
+
 def test_adamw_steps_vs_oracle(tc):
     d = synth.load_desc("student")
     blob = synth.he_weights(d)
