@@ -208,3 +208,26 @@ def test_fallback_switches_to_teacher(tc):
     fw, bw, _ = always(A, B)
     tfw, tbw = t_net.flow_estimate_pair(A, B)
     assert torch.equal(fw, tfw) and torch.equal(bw, tbw) and always.fallbacks == 1
+
+
+def test_fallback_threshold_boundary(tc):
+    """The rule falls back exactly when the agreement is below the threshold:
+    thresholds half a pixel's share above and below the measured agreement
+    of a pair flip the decision (agreement = agreeing pixels / h w)."""
+    from paper_2301_00750_amd import student
+    sd, td = synth.load_desc("student"), synth.load_desc("tiny")
+    s_net, t_net = tc.Net(sd, synth.he_weights(sd)), tc.Net(td, synth.he_weights(td))
+    h, w = 64, 96
+    A, B, _ = batch(1, h, w, 7)
+    A, B = A.cuda().contiguous(), B.cuda().contiguous()
+    _, _, agree = student.FallbackFlow(s_net, t_net, h, w, threshold=0.0)(A, B)
+    say(f"[fallback] agreement {agree:.6f} ({round(agree * h * w)} of {h * w} pixels)")
+    half = 0.5 / (h * w)
+    above = student.FallbackFlow(s_net, t_net, h, w, threshold=agree + half)
+    fw, _, _ = above(A, B)
+    assert above.fallbacks == 1 and torch.equal(fw, t_net.flow_estimate_pair(A, B)[0])
+    if agree > 0.0:
+        below = student.FallbackFlow(s_net, t_net, h, w, threshold=agree - half)
+        fw, _, _ = below(A, B)
+        assert below.fallbacks == 0 and torch.equal(fw, s_net.flow_estimate_pair(A, B)[0])
+
