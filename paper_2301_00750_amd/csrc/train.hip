@@ -985,7 +985,7 @@ int tconv(const tc_trainer* t, const float* w, const float* b, int cout, int np,
   a.n = n;
   a.partial = t->cpart;
   hipError_t e;
-  if (wu4) {
+  if (wu4 && stride == 1 && kc == 8) {
     // F(4x4) Winograd weights packed for C_out rounded up to 32
     a.np = (cout + 31) / 32 * 32;
     a.splits = 1;
