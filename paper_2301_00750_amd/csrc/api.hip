@@ -1205,7 +1205,7 @@ int tc_consistency_paper(const float* I_prev, const float* I, const float* I_nex
   a.O3 = reinterpret_cast<float*>(base + 13 * pl);
   hipStream_t s = (hipStream_t)stream;
   probe_begin(TC_STAGE_PAPER, s);
-  const hipError_t e = launch_paper_step(a, out, 6, s);
+  const hipError_t e = launch_paper_step(a, out, 7, s);
   probe_end(TC_STAGE_PAPER, s);
   return e == hipSuccess ? TC_OK : TC_ERR_HIP;
 }

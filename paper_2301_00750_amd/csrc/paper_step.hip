@@ -7,11 +7,13 @@
 // (5-point Laplacian, Neumann borders), and one iteration is
 //   O' = O - eta grad E(O) + kappa (O - O_old).
 // The iterations are temporally blocked: a workgroup loads a 64 x 48 region
-// (one column per lane group, 12 rows per thread, values in registers),
-// exchanges the 4-neighbours through LDS and runs K iterations; after K
-// iterations the region's border of width K holds stale values and only the
-// interior (64 - 2K) x (48 - 2K) is written back.  Border pixels of the image
-// use only their in-image neighbours.
+// (wave w a 64 x 12 strip, one column per lane, its 12 rows in registers),
+// takes the horizontal neighbours by DPP wave shifts, the vertical ones from
+// its own registers and, at a strip's first and last row, from the
+// neighbouring strip through LDS, and runs K iterations (7 per pass); after
+// K iterations the region's border of width K holds stale values and only
+// the interior (64 - 2K) x (48 - 2K) is written back.  Border pixels of the
+// image use only their in-image neighbours.
 #include "tc_internal.h"
 
 namespace tc {
