@@ -136,16 +136,36 @@ __device__ inline u2v pack8_fp8(const float (&v)[8], float inv_scale) {
   return u2v{(unsigned)lo, (unsigned)hi};
 }
 
-// 8 floats -> 8 FP8 E4M3 after multiplying by `inv_scale`, without clamping:
-// for callers whose |v| * inv_scale is at most 448 by construction (an
-// input scale derived from a bound of |v|, with margin for the rounding of
-// the stored values).
-__device__ inline u2v pack8_fp8_nosat(const float (&v)[8], float inv_scale) {
-  int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0] * inv_scale, v[1] * inv_scale, 0, false);
-  lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[2] * inv_scale, v[3] * inv_scale, lo, true);
-  int hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[4] * inv_scale, v[5] * inv_scale, 0, false);
-  hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[6] * inv_scale, v[7] * inv_scale, hi, true);
-  return u2v{(unsigned)lo, (unsigned)hi};
+// One 16-byte word of 8 bfloat16 (f16 = false) or float16 values to 8 FP8
+// E4M3 bytes, each value divided by s, by gfx950's scaled packed conversions
+// (two values per instruction).  The instruction applies only the exponent
+// of its scale, so s must be a power of two; a quotient beyond 448 becomes
+// NaN, so s must bound the values.  The word's components are copied to
+// scalars before the bit casts (a bit cast of a vector element can read
+// element 0).
+__device__ inline u2v word_to_fp8_pow2(u4 w, bool f16, float s) {
+  typedef short s2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+  const unsigned c[4] = {w.x, w.y, w.z, w.w};
+  s2 lo = {0, 0}, hi = {0, 0};
+  if (f16) {
+    lo = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(lo, __builtin_bit_cast(h2, c[0]), s, false);
+    lo = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(lo, __builtin_bit_cast(h2, c[1]), s, true);
+    hi = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(hi, __builtin_bit_cast(h2, c[2]), s, false);
+    hi = __builtin_amdgcn_cvt_scalef32_pk_fp8_f16(hi, __builtin_bit_cast(h2, c[3]), s, true);
+  } else {
+    lo = __builtin_amdgcn_cvt_scalef32_pk_fp8_bf16(lo, __builtin_bit_cast(b2, c[0]), s, false);
+    lo = __builtin_amdgcn_cvt_scalef32_pk_fp8_bf16(lo, __builtin_bit_cast(b2, c[1]), s, true);
+    hi = __builtin_amdgcn_cvt_scalef32_pk_fp8_bf16(hi, __builtin_bit_cast(b2, c[2]), s, false);
+    hi = __builtin_amdgcn_cvt_scalef32_pk_fp8_bf16(hi, __builtin_bit_cast(b2, c[3]), s, true);
+  }
+  return u2v{__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi)};
+}
+
+// The power of two at or above q > 0 (q normal)
+__device__ inline float pow2_ceil(float q) {
+  const unsigned b = __builtin_bit_cast(unsigned, q);
+  return (b & 0x007fffffu) ? __builtin_bit_cast(float, (b & 0x7f800000u) + 0x00800000u) : q;
 }
 
 // Each image's absolute maximum is spread over kAmaxSub sub-slots, each on

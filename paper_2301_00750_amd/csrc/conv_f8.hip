@@ -85,16 +85,13 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f8k128(ConvArgs a, const unsig
 
   // Input scale: the stored inputs are the producers' values rounded to
   // bfloat16 or float16, at most 2^-8 above the recorded maximum m in
-  // magnitude, so x * 448 / (m (1 + 2^-7)) stays within 448 and the FP8
-  // conversion needs no clamp.
-  float sa = 1.f, inv_sa = 1.f;
+  // magnitude; the scale is the power of two at or above m (1 + 2^-7) / 448,
+  // so every x / sa stays within 448 (the largest lands in (224, 448]) and
+  // the scaled conversion applies it exactly.
+  float sa = 1.f;
   {
     const float m = fmaxf(f8_amax_of(a.ain[0], img), fmaxf(f8_amax_of(a.ain[1], img), f8_amax_of(a.ain[2], img)));
-    if (m > 0.f && m < 3.0e38f) {
-      const float mm = m * (1.f + 0.0078125f);
-      sa = mm / kFp8Max;
-      inv_sa = kFp8Max / mm;
-    }
+    if (m > 1.0e-30f && m < 3.0e38f) sa = pow2_ceil(m * (1.f + 0.0078125f) / kFp8Max);
   }
 
   // The weights of a step are fetched PD steps ahead into a ring of register
@@ -163,14 +160,9 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f8k128(ConvArgs a, const unsig
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int blk = b0 + u;
-          if (blk < nblk) {
-            float f[8];
-            if ((a.in_f16 >> (blk < a.nb0 ? 0 : 1)) & 1)
-              unpack8h(v[u], f);
-            else
-              load8(reinterpret_cast<const bf16*>(&v[u]), f);
-            reinterpret_cast<u2v*>(sA)[blk * NPOS + pos] = pack8_fp8_nosat(f, inv_sa);
-          }
+          if (blk < nblk)
+            reinterpret_cast<u2v*>(sA)[blk * NPOS + pos] =
+                word_to_fp8_pow2(v[u], (a.in_f16 >> (blk < a.nb0 ? 0 : 1)) & 1, sa);
         }
       }
     }
