@@ -41,7 +41,7 @@ typedef enum {
   TC_ERR_INVALID_ARG = 1, /* null pointer, n/h/w <= 0, alpha outside [0,1] or NaN */
   TC_ERR_SHAPE = 2,       /* descriptor or weight count inconsistent           */
   TC_ERR_WORKSPACE = 3,   /* workspace / pyramid buffer too small or unaligned */
-  TC_ERR_UNSUPPORTED = 4, /* precision or size this build does not handle      */
+  TC_ERR_UNSUPPORTED = 4, /* precision or size the library does not handle     */
   TC_ERR_HIP = 5,         /* a HIP runtime call or kernel launch failed        */
   TC_ERR_SCRATCH = 6      /* input too large for the static scratch of
                              tc_flow_estimate_pair_noalloc                      */
