@@ -140,6 +140,28 @@ def test_gradient_vs_oracle_winograd_level():
     assert worst <= 1e-3
 
 
+def test_gradient_vs_oracle_wide_decoder(tc):
+    """A decoder of 96/64/32 channels: the weight gradient splits c1's and
+    c2's output channels over two groups of 48 (the second group of c2 holds
+    one block of 16), which the student's 48/32/16 never does."""
+    d = dict(synth.load_desc("student"), ch=[16, 24, 32], dec=[96, 64, 32])
+    blob = synth.he_weights(d)
+    A, B, T = batch(2, 40, 56, 13)
+    say("[train] gradient 2 x 40x56, decoder 96/64/32")
+    tr = tc.Trainer(d, blob, 2, 40, 56)
+    loss = tr.grad(A.cuda().contiguous(), B.cuda().contiguous(), T.cuda().contiguous())
+    g = tr.copy(1).cpu().double().numpy()
+    lref, gref = S.loss_and_grad(blob.astype(np.float64), A.double(), B.double(), T.double(), d)
+    say(f"   loss gpu={float(loss):.7f} oracle={lref:.7f}")
+    assert abs(float(loss) - lref) <= 1e-5 * abs(lref)
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    worst = max(np.abs(g[a:b] - gref[a:b]).max() / max(np.abs(gref[a:b]).max(), 1e-12)
+                for _, a, b in layer_slices(d, blob))
+    say(f"   gradient relative L2 error {rel:.2e}, worst layer {worst:.2e}")
+    assert rel <= 1e-4
+    assert worst <= 1e-3
+
+
 def test_adamw_steps_vs_oracle(tc):
     d = synth.load_desc("student")
     blob = synth.he_weights(d)
