@@ -116,17 +116,20 @@ def test_gradient_vs_oracle_wide_flows(tc):
     assert worst <= 1e-3
 
 
-def test_gradient_vs_oracle_winograd_level():
+@pytest.mark.parametrize("hw", [(512, 1024), (520, 1000)])
+def test_gradient_vs_oracle_winograd_level(hw):
     """At 512 x 1024 level 1 (256 x 512) has 256 regions of 16 x 32 pixels, so
     the trainer runs its c1 and c2 forward and its c1, c2 and c3 data
     gradients there through the F(4x4) Winograd conv (weights transformed on
-    the device from the current blob every call); level 2 stays direct."""
+    the device from the current blob every call); level 2 stays direct.
+    520 x 1000: level 1 is 260 x 500, ragged against the 16 x 32 regions."""
     from paper_2301_00750_amd import tcflow as tc
+    h, w = hw
     d = synth.load_desc("student")
     blob = synth.he_weights(d)
-    A, B, T = batch(1, 512, 1024, 21)
-    say("[train] gradient 1 x 512x1024 (Winograd on level 1)")
-    tr = tc.Trainer(d, blob, 1, 512, 1024)
+    A, B, T = batch(1, h, w, 21)
+    say(f"[train] gradient 1 x {h}x{w} (Winograd on level 1)")
+    tr = tc.Trainer(d, blob, 1, h, w)
     loss = tr.grad(A.cuda().contiguous(), B.cuda().contiguous(), T.cuda().contiguous())
     g = tr.copy(1).cpu().double().numpy()
     lref, gref = S.loss_and_grad(blob.astype(np.float64), A.double(), B.double(), T.double(), d)
