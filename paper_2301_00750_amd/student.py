@@ -131,6 +131,9 @@ def main():
     ap.add_argument("--pairs", type=int, default=None)
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--init", default=None,
+                    help="start from these weights (a fine-tuning stage) instead of He init")
+    ap.add_argument("--lr", type=float, default=None, help="learning rate (default: the config's)")
     args = ap.parse_args()
     sd = synth.load_desc("student")
     td = synth.load_desc("fullhd")
@@ -146,14 +149,24 @@ def main():
     Tfw, Tbw = teacher_flows(teacher, A, B)
     torch.cuda.synchronize()
     log(f"data + teacher flows: {time.perf_counter() - t0:.1f} s")
-    prm = tcflow.train_params(lr=tp["lr"], beta1=tp["beta1"], beta2=tp["beta2"], eps=tp["eps"],
+    lr = args.lr if args.lr is not None else tp["lr"]
+    prm = tcflow.train_params(lr=lr, beta1=tp["beta1"], beta2=tp["beta2"], eps=tp["eps"],
                               weight_decay=tp["weight_decay"], loss_eps=tp["loss_eps"],
                               loss_q=tp["loss_q"])
-    wts, hist, secs = train(sd, A, B, Tfw, Tbw, steps, batch, params=prm)
+    init = np.load(args.init, allow_pickle=False) if args.init else None
+    prior = []
+    if args.init:
+        prior_meta = os.path.splitext(args.init)[0] + ".json"
+        if os.path.exists(prior_meta):
+            prior = json.load(open(prior_meta)).get("stages", [])
+    wts, hist, secs = train(sd, A, B, Tfw, Tbw, steps, batch, params=prm, weights=init)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, wts.astype(np.float32), allow_pickle=False)
-    meta = dict(steps=steps, pairs=pairs, batch=batch, resolution=[w, h], train_seconds=secs,
-                step_ms=1e3 * secs / max(1, steps), loss_history=hist, params=tp)
+    stage = dict(steps=steps, lr=lr, init="he" if init is None else "previous stage",
+                 train_seconds=secs, step_ms=1e3 * secs / max(1, steps), loss_history=hist)
+    meta = dict(steps=sum(st["steps"] for st in prior) + steps, pairs=pairs, batch=batch,
+                resolution=[w, h], train_seconds=secs, step_ms=1e3 * secs / max(1, steps),
+                loss_history=hist, params=tp, stages=prior + [stage])
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(meta, f, indent=1)
     log(f"saved {args.out}: {steps} steps in {secs:.1f} s ({meta['step_ms']:.2f} ms/step)")
