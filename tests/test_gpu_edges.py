@@ -93,6 +93,31 @@ def student_4k_case():
     return _4K
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("level", [0.0, 0.5])
+def test_precision_forms_flat_frames(tc, prec, level):
+    """Flat frames through the precision forms: all-zero inputs give a zero
+    per-image maximum (the FP8 input scale falls back to 1), a constant
+    frame a single value everywhere; the flows stay finite and within the
+    forms' bar of the oracle's."""
+    p = {"bf16": tc.TC_BF16, "fp8": tc.TC_FP8_E4M3}[prec]
+    d = synth.load_desc("tiny")
+    blob = synth.he_weights(d)
+    wts = O.unpack_weights(blob, d)
+    net = tc.Net(d, blob, precision=p)
+    h, w = 64, 96
+    A = torch.full((1, 3, h, w), level)
+    say(f"[edge] {prec} flat frames at {level}")
+    fw, bw = net.flow_estimate_pair(A.cuda(), A.cuda())
+    torch.cuda.synchronize()
+    assert torch.isfinite(fw).all() and torch.isfinite(bw).all()
+    rfw, rbw = O.flow_pair(f64(A[0]), f64(A[0]), wts, d)
+    for a, b in ((fw[0], rfw), (bw[0], rbw)):
+        mean, mx = epe(a, b)
+        say(f"   EPE mean {mean:.3e} max {mx:.3e}")
+        assert mean <= 0.25 and mx <= 1.0, (prec, level, mean, mx)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_student_4k_vs_oracle(tc, prec):
     """The trained student at 3840 x 2160 against the numpy oracle of the same
