@@ -162,7 +162,7 @@ def main():
     wts, hist, secs = train(sd, A, B, Tfw, Tbw, steps, batch, params=prm, weights=init)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, wts.astype(np.float32), allow_pickle=False)
-    stage = dict(steps=steps, lr=lr, init="he" if init is None else "previous stage",
+    stage = dict(steps=steps, lr=lr, pairs=pairs, init="he" if init is None else "previous stage",
                  train_seconds=secs, step_ms=1e3 * secs / max(1, steps), loss_history=hist)
     meta = dict(steps=sum(st["steps"] for st in prior) + steps, pairs=pairs, batch=batch,
                 resolution=[w, h], train_seconds=secs, step_ms=1e3 * secs / max(1, steps),
