@@ -497,6 +497,11 @@ __global__ __launch_bounds__(256) void head_kernel(ConvArgs a) {
 // four lane groups of consecutive MFMA steps, so a step can span two taps and
 // no tap is padded to 32 channels.  The weights of a chunk are packed
 // [step][lane group][n][8 k] so one 16-byte LDS read is one B fragment.
+// BF16: a chunk's weights are copied straight from global memory into LDS
+// (global_load_lds, 1 KB per wave instruction) once every wave has finished
+// the previous chunk, while only the input halo passes through registers; the
+// registers this frees let three workgroups share a CU where the accumulators
+// allow it (MR * NB <= 24), and their MFMAs cover each other's copy latency.
 // F8: the same walk with FP8 E4M3 operands (v_mfma_f32_16x16x32_fp8_fp8, 8
 // bytes per lane): the BF16 input is scaled by 448 / max|x| of its image and
 // rounded to FP8 when staged, weights are FP8 per output channel, and the
@@ -508,7 +513,7 @@ __device__ inline float amax_of(const AmaxIn& m, int img) {
 }
 
 template <int S, int NB, int MR, bool F8>
-__global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
+__global__ __launch_bounds__(256, (F8 || MR * NB > 24) ? 2 : 3) void conv3x3_bf16_mfma(ConvArgs a) {
   using W = std::conditional_t<F8, u2v, u4>;  // one operand word: 8 values
   constexpr int TH = 4 * MR;
   constexpr int IH = (TH - 1) * S + 3, IW = (TW - 1) * S + 3;
@@ -517,6 +522,9 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
   constexpr int NA = BF_CPC * NPOS;        // operand words of input per chunk
   constexpr int NBW = BF_STEPS * 4 * NP;   // operand words of weights per chunk
   constexpr int RA = (NA + 255) / 256, RB = (NBW + 255) / 256;
+  // BF16: weights by direct global-to-LDS loads, 1 KB per wave instruction
+  constexpr bool DMA = !F8 && (NBW * sizeof(W)) % 1024 == 0;
+  constexpr int WPIECES = (int)(NBW * sizeof(W) / 1024);
   __shared__ __attribute__((aligned(16))) W sA[NA];
   __shared__ __attribute__((aligned(16))) W sB[NBW];
 
@@ -591,11 +599,24 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
       }
       ra[j] = val;
     }
-    const W* wsrc = reinterpret_cast<const W*>(a.w) + (size_t)ch * NBW;
+    if constexpr (!DMA) {
+      const W* wsrc = reinterpret_cast<const W*>(a.w) + (size_t)ch * NBW;
 #pragma unroll
-    for (int j = 0; j < RB; ++j) {
-      const int i = tid + j * 256;
-      rb[j] = i < NBW ? wsrc[i] : W{};
+      for (int j = 0; j < RB; ++j) {
+        const int i = tid + j * 256;
+        rb[j] = i < NBW ? wsrc[i] : W{};
+      }
+    }
+  };
+  auto fetch_w = [&](int ch) {
+    if constexpr (DMA) {
+      const int w0 = __builtin_amdgcn_readfirstlane(wave);
+      const char* src = reinterpret_cast<const char*>(reinterpret_cast<const W*>(a.w) + (size_t)ch * NBW) + lane * 16;
+#pragma unroll
+      for (int kb = w0; kb < WPIECES; kb += 4)
+        __builtin_amdgcn_global_load_lds(
+            reinterpret_cast<const void*>(src + kb * 1024),
+            (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(sB) + kb * 1024), 16, 0, 0);
     }
   };
   auto stash = [&]() {
@@ -616,16 +637,22 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
         }
       }
     }
+    if constexpr (!DMA) {
 #pragma unroll
-    for (int j = 0; j < RB; ++j) {
-      const int i = tid + j * 256;
-      if (i < NBW) sB[i] = rb[j];
+      for (int j = 0; j < RB; ++j) {
+        const int i = tid + j * 256;
+        if (i < NBW) sB[i] = rb[j];
+      }
     }
   };
 
-  if (c_begin < c_end) fetch(c_begin);
+  if (c_begin < c_end) {
+    fetch(c_begin);
+    fetch_w(c_begin);
+  }
   for (int ch = c_begin; ch < c_end; ++ch) {
     stash();
+    if constexpr (DMA) __builtin_amdgcn_s_waitcnt(0);  // this wave's weight pieces are in LDS
     __syncthreads();
     if (ch + 1 < c_end) fetch(ch + 1);
     const bool full = nblk - ch * BF_CPC >= BF_CPC;
@@ -654,6 +681,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_bf16_mfma(ConvArgs a) {
       }
     }
     __syncthreads();
+    if (ch + 1 < c_end) fetch_w(ch + 1);
   }
 
   float mx = 0.f;
