@@ -530,17 +530,9 @@ __global__ __launch_bounds__(256, (F8 || MR * NB > 24) ? 2 : 3) void conv3x3_bf1
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  // XCD-aware tile order: workgroup b (x fastest, then y, then z) runs on XCD
-  // b % 8; each XCD takes a contiguous row-major range of tiles, so the halo
-  // shared by neighbouring tiles is read once into that XCD's L2.
-  const int gxy = gridDim.x * gridDim.y, total = gxy * gridDim.z;
-  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  const int xq = total / 8, xr = total % 8, xc = bid % 8;
-  const int wid = (xc < xr ? xc * (xq + 1) : xr * (xq + 1) + (xc - xr) * xq) + bid / 8;
-  const int bz = wid / gxy, bxy = wid - bz * gxy;
-  const int by = bxy / gridDim.x, bx = bxy - by * gridDim.x;
-  const int tx0 = bx * TW, ty0 = by * TH;
-  const int img = bz / a.splits, split = bz - img * a.splits;
+  const uint3 tile = xcd_tile();
+  const int tx0 = tile.x * TW, ty0 = tile.y * TH;
+  const int img = tile.z / a.splits, split = tile.z - img * a.splits;
   const int iy0 = ty0 * S - 1, ix0 = tx0 * S - 1;
   const size_t in_plane = (size_t)a.in_h * a.in_w * 8;
   const int c_begin = split * a.cps;

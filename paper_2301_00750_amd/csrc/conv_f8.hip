@@ -78,15 +78,9 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f8k128(ConvArgs a, const unsig
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lm = lane & 15, lk = lane >> 4;
-  // XCD-aware tile order (workgroup b runs on XCD b % 8; each XCD takes a
-  // contiguous row-major range of tiles and shares their halo in its L2)
-  const int gxy = gridDim.x * gridDim.y, total = gxy * gridDim.z;
-  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  const int xq = total / 8, xr = total % 8, xc = bid % 8;
-  const int wid = (xc < xr ? xc * (xq + 1) : xr * (xq + 1) + (xc - xr) * xq) + bid / 8;
-  const int img = wid / gxy, bxy = wid - img * gxy;
-  const int by = bxy / gridDim.x, bx = bxy - by * gridDim.x;
-  const int tx0 = bx * Q8_TW, ty0 = by * TH;
+  const uint3 tile = xcd_tile();
+  const int img = tile.z;
+  const int tx0 = tile.x * Q8_TW, ty0 = tile.y * TH;
   const int iy0 = ty0 * S - 1, ix0 = tx0 * S - 1;
   const size_t in_plane = (size_t)a.in_h * a.in_w * 8;
 

@@ -13,7 +13,8 @@
 // neighbouring strip through LDS, and runs K iterations (7 per pass); after
 // K iterations the region's border of width K holds stale values and only
 // the interior (64 - 2K) x (48 - 2K) is written back.  Border pixels of the
-// image use only their in-image neighbours.
+// image use only their in-image neighbours.  Regions run in XCD-aware order,
+// so the overlapping borders of neighbouring regions are read into one L2.
 #include "tc_internal.h"
 
 namespace tc {
@@ -129,9 +130,10 @@ __global__ __launch_bounds__(256) void paper_solve_kernel(PaperArgs a, const flo
   __shared__ float sx[2][4][2][3][RW];  // [parity][wave][first / last row][channel][column]
   const int tx = threadIdx.x & 63, tg = threadIdx.x >> 6;
   const int TWo = RW - 2 * K, THo = RH - 2 * K;
-  const int img = blockIdx.z;
-  const int gx = blockIdx.x * TWo - K + tx;
-  const int gy0 = blockIdx.y * THo - K + tg * PPT;
+  const uint3 tile = xcd_tile();
+  const int img = tile.z;
+  const int gx = tile.x * TWo - K + tx;
+  const int gy0 = tile.y * THo - K + tg * PPT;
   const size_t plane = (size_t)a.h * a.w;
   const size_t o3 = (size_t)img * 3 * plane;
   const bool colin = gx >= 0 && gx < a.w;

@@ -249,4 +249,18 @@ hipError_t launch_consistency(const float* P, const float* Oprev, const float* f
                               const float* fbw, float alpha, int n, int h, int w, float* out,
                               unsigned char* mask, hipStream_t s);
 
+// XCD-aware tile order.  Workgroup b of a grid (x fastest, then y, then z)
+// runs on XCD b % 8 of the eight; each XCD is given a contiguous row-major
+// range of the grid's tiles, so the halo that neighbouring tiles share is read
+// into one L2.  Returns the tile (x, y, z) this workgroup computes (a
+// bijection of the grid).
+__device__ inline uint3 xcd_tile() {
+  const unsigned gxy = gridDim.x * gridDim.y, total = gxy * gridDim.z;
+  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned q = total / 8, r = total % 8, xc = bid % 8;
+  const unsigned wid = (xc < r ? xc * (q + 1) : r * (q + 1) + (xc - r) * q) + bid / 8;
+  const unsigned z = wid / gxy, xy = wid - z * gxy, y = xy / gridDim.x;
+  return make_uint3(xy - y * gridDim.x, y, z);
+}
+
 }  // namespace tc
