@@ -9,6 +9,16 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 typedef unsigned short bf16;  // storage type of bfloat16 activations
 
+// Orders the LDS accesses of one wave's lanes around it: lanes of a wave that
+// exchange data through a region only that wave touches need no workgroup
+// barrier (a wave's LDS instructions run in order), only this compiler-level
+// ordering.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline float bf2f(bf16 h) { return __uint_as_float((unsigned)h << 16); }
 
 // Load through the global address space (global_load_*).  Pointers picked

@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_mfma(ConvArgs a) {
 #pragma unroll
     for (int mb = 0; mb < MR; ++mb) {
       const int oy = ty0 + wave * MR + mb;
-      __syncthreads();
+      wave_lds_sync();  // the wave's own staging region
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const int n = nb * 16 + lm;
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_mfma(ConvArgs a) {
           so[(4 * lk + vv) * NPS + n] = v;
         }
       }
-      __syncthreads();
+      wave_lds_sync();  // the wave's own staging region
       if (oy < a.out_h) {
         for (int e = lane; e < TW * (NP / 8); e += 64) {
           const int px = e / (NP / 8), blk = e - (e / (NP / 8)) * (NP / 8);
@@ -707,7 +707,7 @@ __global__ __launch_bounds__(256, (F8 || MR * NB > 24) ? 2 : 3) void conv3x3_bf1
 #pragma unroll
     for (int mb = 0; mb < MR; ++mb) {
       const int oy = ty0 + wave * MR + mb;
-      __syncthreads();
+      wave_lds_sync();  // the wave's own staging region
       float y[NB][4];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
@@ -735,7 +735,7 @@ __global__ __launch_bounds__(256, (F8 || MR * NB > 24) ? 2 : 3) void conv3x3_bf1
 #pragma unroll
           for (int vv = 0; vv < 4; ++vv) so[(4 * lk + vv) * NP + nb * 16 + lm] = f2bf(y[nb][vv]);
       }
-      __syncthreads();
+      wave_lds_sync();  // the wave's own staging region
       if (oy < a.out_h) {
         for (int e = lane; e < TW * (NP / 8); e += 64) {
           const int px = e / (NP / 8), blk = e - (e / (NP / 8)) * (NP / 8);

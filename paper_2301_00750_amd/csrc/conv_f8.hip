@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f8k128(ConvArgs a, const unsig
 #pragma unroll
   for (int mb = 0; mb < MR; ++mb) {
     const int oy = ty0 + wave * MR + mb;
-    __syncthreads();
+    wave_lds_sync();  // the wave's own staging region
     float y[NB][4];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f8k128(ConvArgs a, const unsig
 #pragma unroll
         for (int vv = 0; vv < 4; ++vv) so[(4 * lk + vv) * NP + nb * 16 + lm] = f2bf(y[nb][vv]);
     }
-    __syncthreads();
+    wave_lds_sync();  // the wave's own staging region
     if (oy < a.out_h) {
       for (int e = lane; e < Q8_TW * (NP / 8); e += 64) {
         const int px = e / (NP / 8), blk = e - (e / (NP / 8)) * (NP / 8);

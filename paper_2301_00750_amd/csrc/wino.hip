@@ -236,7 +236,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_wino(ConvArgs a, const flo
         so[(lr * WT + lc + 1) * WOP + lm] = y1;
       }
     }
-    __syncthreads();
+    wave_lds_sync();  // the wave's own staging region
     // 64 pixels x 2 blocks of 8 channels per wave
 #pragma unroll
     for (int e = lane; e < 128; e += 64) {
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f32_wino(ConvArgs a, const flo
         dst[1] = src[1];
       }
     }
-    __syncthreads();
+    wave_lds_sync();  // the wave's own staging region
   }
 }
 

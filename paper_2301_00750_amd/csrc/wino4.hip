@@ -303,7 +303,7 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
         }
       }
     }
-    __syncthreads();
+    wave_lds_sync();  // the wave's own staging region
     // 64 pixels x 2 blocks of 8 channels per wave
 #pragma unroll
     for (int e = lane; e < 128; e += 64) {
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(128 * QM, 4 / QM) void conv3x3_f32_wino4(ConvArgs a
         dst[1] = src[1];
       }
     }
-    __syncthreads();
+    wave_lds_sync();  // the wave's own staging region
   }
 }
 
