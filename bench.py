@@ -42,7 +42,7 @@ ALPHAS = (0.0, 0.25, 0.5, 0.75, 1.0)
 # HBM bytes per launch of the level-1 conv1 at 1920x1080 (fw + bw), from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE scaled by a 1 GiB copy measured in the same runs (profiles/); valid only while the conv
 # source is the one they were measured on.
-CONV1_TRAFFIC = {"bytes": 1.0547e9, "source": "wino4.hip", "sha256_16": "db3d03ef732782c6"}
+CONV1_TRAFFIC = {"bytes": 1.0535e9, "source": "wino4.hip", "sha256_16": "f6462c558316c6c0"}
 METRIC = "1080p frames/s (flow+consistency) at stated EPE vs FP64 oracle; p99 frame ms"
 
 
