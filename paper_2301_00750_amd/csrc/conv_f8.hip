@@ -230,6 +230,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f8k128(ConvArgs a, const unsig
   // LeakyReLU as max(v, slope v) (0 <= slope <= 1); slope 1 = no activation
   const float slope = a.lrelu ? a.slope : 1.f;
   const bool track = a.aout != nullptr;
+  const bool tile_full = tx0 + Q8_TW <= a.out_w && a.cout == NP;  // all columns and channels real
   float osc[NB], bn[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
@@ -250,11 +251,18 @@ __global__ __launch_bounds__(256, 2) void conv3x3_f8k128(ConvArgs a, const unsig
         y[nb][vv] = fmaxf(v, slope * v);
       }
     if (track && oy < a.out_h) {  // amax of the stored outputs (real channels, in the image)
+      if (tile_full) {  // every value of the row is a real output
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
+        for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int vv = 0; vv < 4; ++vv)
-          if (nb * 16 + lm < a.cout && tx0 + 4 * lk + vv < a.out_w) mx = fmaxf(mx, fabsf(y[nb][vv]));
+          for (int vv = 0; vv < 4; ++vv) mx = fmaxf(mx, fabsf(y[nb][vv]));
+      } else {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv)
+            if (nb * 16 + lm < a.cout && tx0 + 4 * lk + vv < a.out_w) mx = fmaxf(mx, fabsf(y[nb][vv]));
+      }
     }
     if (a.out_f16) {
 #pragma unroll
